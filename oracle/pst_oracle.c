@@ -1,0 +1,602 @@
+/*
+ * Plain FP64 CPU oracle for the pseudospectral Navier-Stokes / MHD hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant with
+ * the HIP path.
+ *
+ * Everything here is written to be checked by eye against the paper
+ * (Rosenberg, Mininni, Reddy, Pouquet, "GPU parallelization of a hybrid
+ * pseudospectral fluid turbulence framework using CUDA"):
+ *
+ *   - the discrete Fourier expansion and its sign convention:
+ *     Sec. 2, eq. (fftsum) and the sentence after it (backward = sign change);
+ *   - real-to-complex storage of (Nx/2+1) x Ny x Nz coefficients with the
+ *     Hermitian relation for real data: Sec. 2, forward-transform steps;
+ *   - the forward transform as x then y then z one-dimensional transforms and
+ *     the backward transform as the same steps reversed: Sec. 2, steps 1-3;
+ *   - products of the nonlinear terms in physical space, pressure by
+ *     projection onto divergence-free fields: Sec. 2, paragraph after
+ *     eq. (fftsum);
+ *   - the incompressible Navier-Stokes equations (eq. mom + eq. divv with
+ *     theta = 0) and MHD (eq. uMHD, eq. bMHD);
+ *   - explicit Runge-Kutta time stepping of order 2-4: Sec. 2.
+ *
+ * Readings where the paper is silent (normalisation, dealiasing rule,
+ * integrating factor, RK variant, shell binning) are the ones listed in the
+ * design notes: forward transform carries 1/(Nx Ny Nz) so that
+ * u(x) = sum_k uhat(k) exp(i k.x); backward is unscaled; cube truncation with
+ * K = ceil(N/3) - 1; Lawson integrating factor with Heun RK2 / classical RK4;
+ * shell n = floor(|k| + 1/2).
+ *
+ * The FFT is the textbook recursive mixed-radix Cooley-Tukey (Cooley & Tukey
+ * 1965) over factors 2 and 3, with a naive O(n^2) DFT for any other factor.
+ * No blocking, fusion or reordering beyond that.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------------ */
+/* 1D transforms                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Naive DFT, the definition itself: X[k] = sum_j x[j] exp(sign 2 pi i j k / n). */
+void ora_dft_naive(int n, const double *in, double *out, int sign)
+{
+    const cplx *x = (const cplx *)in;
+    cplx *X = (cplx *)out;
+    for (int k = 0; k < n; ++k) {
+        cplx acc = 0;
+        for (int j = 0; j < n; ++j) {
+            long m = ((long)j * k) % n;
+            double ang = sign * 2.0 * M_PI * (double)m / (double)n;
+            acc += x[j] * (cos(ang) + I * sin(ang));
+        }
+        X[k] = acc;
+    }
+}
+
+static int smallest_factor(int n)
+{
+    if (n % 2 == 0) return 2;
+    if (n % 3 == 0) return 3;
+    return n; /* anything else is done by the naive DFT */
+}
+
+/* Recursive decimation-in-time Cooley-Tukey.
+ * in  : input sequence of length n with element stride s
+ * out : contiguous output of length n
+ * tw  : tw[m] = exp(sign 2 pi i m / L) for the top-level length L
+ * step: L / n, so that w_n^j = tw[j * step]                                   */
+static void fft_rec(const cplx *in, int s, cplx *out, int n, const cplx *tw, int step)
+{
+    if (n == 1) { out[0] = in[0]; return; }
+    int p = smallest_factor(n);
+    if (p == n) {
+        for (int k = 0; k < n; ++k) {
+            cplx acc = 0;
+            for (int j = 0; j < n; ++j)
+                acc += in[(long)j * s] * tw[(((long)j * k) % n) * step];
+            out[k] = acc;
+        }
+        return;
+    }
+    int m = n / p;
+    /* Y_q[k] = sum_{j<m} x[p j + q] w_m^{j k}, stored at out[q m + k] */
+    for (int q = 0; q < p; ++q)
+        fft_rec(in + (long)q * s, s * p, out + (long)q * m, m, tw, step * p);
+    /* X[k + m t] = sum_q w_n^{q (k + m t)} Y_q[k]; the p outputs of a given k
+     * occupy exactly the p slots its inputs came from, so it is done in place */
+    cplx a[3];
+    for (int k = 0; k < m; ++k) {
+        for (int q = 0; q < p; ++q) a[q] = out[(long)q * m + k];
+        for (int t = 0; t < p; ++t) {
+            cplx acc = 0;
+            for (int q = 0; q < p; ++q)
+                acc += tw[(((long)q * (k + (long)m * t)) % n) * step] * a[q];
+            out[k + (long)m * t] = acc;
+        }
+    }
+}
+
+static cplx *roots_table(int n, int sign)
+{
+    cplx *tw = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    for (int m = 0; m < n; ++m) {
+        double ang = 2.0 * M_PI * (double)m / (double)n;
+        tw[m] = cos(ang) + I * (sign * sin(ang));
+    }
+    return tw;
+}
+
+/* In-place 1D FFT of n complex numbers (interleaved re/im), unnormalised. */
+void ora_fft1d(int n, double *data, int sign)
+{
+    cplx *x = (cplx *)data;
+    cplx *tw = roots_table(n, sign);
+    cplx *out = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    fft_rec(x, 1, out, n, tw, 1);
+    memcpy(x, out, sizeof(cplx) * (size_t)n);
+    free(out);
+    free(tw);
+}
+
+/* Transform every line of a 3D complex array along one axis.
+ * Lines are gathered into a contiguous buffer, transformed and scattered back. */
+static void c2c_axis(cplx *a, long nlines, int n, long stride,
+                     long (*line_base)(long, const long *), const long *geo, int sign)
+{
+    cplx *tw = roots_table(n, sign);
+#pragma omp parallel
+    {
+        cplx *buf = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+        cplx *out = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+#pragma omp for schedule(static)
+        for (long l = 0; l < nlines; ++l) {
+            long b = line_base(l, geo);
+            for (int j = 0; j < n; ++j) buf[j] = a[b + j * stride];
+            fft_rec(buf, 1, out, n, tw, 1);
+            for (int j = 0; j < n; ++j) a[b + j * stride] = out[j];
+        }
+        free(buf);
+        free(out);
+    }
+    free(tw);
+}
+
+/* geo = {nz, ny, nxh}: complex array [nz][ny][nxh] */
+static long base_y(long l, const long *g) { /* l over (z, kx) */
+    long z = l / g[2], kx = l % g[2];
+    return z * g[1] * g[2] + kx;
+}
+static long base_z(long l, const long *g) { /* l over (y, kx) */
+    return l; /* y * nxh + kx is exactly the flat offset in the first plane */
+}
+static long base_x(long l, const long *g) { /* l over (z, y), full complex rows */
+    return l * g[2];
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3D real <-> complex transforms (layout: real [nz][ny][nx], complex         */
+/* [nz][ny][nx/2+1]; x fastest)                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Forward: x, then y, then z, then scale by 1/(nx ny nz). */
+void ora_r2c3(int nz, int ny, int nx, const double *in, double *out)
+{
+    long nxh = nx / 2 + 1;
+    cplx *o = (cplx *)out;
+    cplx *tw = roots_table(nx, -1);
+#pragma omp parallel
+    {
+        cplx *buf = (cplx *)malloc(sizeof(cplx) * (size_t)nx);
+        cplx *res = (cplx *)malloc(sizeof(cplx) * (size_t)nx);
+#pragma omp for schedule(static)
+        for (long l = 0; l < (long)nz * ny; ++l) {
+            for (int j = 0; j < nx; ++j) buf[j] = in[l * nx + j];
+            fft_rec(buf, 1, res, nx, tw, 1);
+            for (long k = 0; k < nxh; ++k) o[l * nxh + k] = res[k];
+        }
+        free(buf);
+        free(res);
+    }
+    free(tw);
+    long geo[3] = {nz, ny, nxh};
+    c2c_axis(o, (long)nz * nxh, ny, nxh, base_y, geo, -1);
+    c2c_axis(o, (long)ny * nxh, nz, (long)ny * nxh, base_z, geo, -1);
+    double scale = 1.0 / ((double)nx * ny * nz);
+    long tot = (long)nz * ny * nxh;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < tot; ++i) o[i] *= scale;
+}
+
+/* Backward: z, then y, then x (the forward steps reversed), unscaled.  Along
+ * x the half line is extended by X(nx-k) = conj X(k); the self-conjugate
+ * points k = 0 and k = nx/2 keep only their real parts.                      */
+void ora_c2r3(int nz, int ny, int nx, const double *in, double *out)
+{
+    long nxh = nx / 2 + 1;
+    long tot = (long)nz * ny * nxh;
+    cplx *t = (cplx *)malloc(sizeof(cplx) * (size_t)tot);
+    memcpy(t, in, sizeof(cplx) * (size_t)tot);
+    long geo[3] = {nz, ny, nxh};
+    c2c_axis(t, (long)ny * nxh, nz, (long)ny * nxh, base_z, geo, +1);
+    c2c_axis(t, (long)nz * nxh, ny, nxh, base_y, geo, +1);
+    cplx *tw = roots_table(nx, +1);
+#pragma omp parallel
+    {
+        cplx *buf = (cplx *)malloc(sizeof(cplx) * (size_t)nx);
+        cplx *res = (cplx *)malloc(sizeof(cplx) * (size_t)nx);
+#pragma omp for schedule(static)
+        for (long l = 0; l < (long)nz * ny; ++l) {
+            const cplx *h = t + l * nxh;
+            for (int k = 0; k < nx; ++k) {
+                if (k == 0) buf[k] = creal(h[0]);
+                else if (2 * k == nx) buf[k] = creal(h[k]);
+                else if (k < nxh) buf[k] = h[k];
+                else buf[k] = conj(h[nx - k]);
+            }
+            fft_rec(buf, 1, res, nx, tw, 1);
+            for (int j = 0; j < nx; ++j) out[l * nx + j] = creal(res[j]);
+        }
+        free(buf);
+        free(res);
+    }
+    free(tw);
+    free(t);
+}
+
+/* Full complex 3D transform [nz][ny][nx], unnormalised, for tests. */
+void ora_c2c3(int nz, int ny, int nx, double *data, int sign)
+{
+    cplx *a = (cplx *)data;
+    long geo[3] = {nz, ny, nx};
+    c2c_axis(a, (long)nz * ny, nx, 1, base_x, geo, sign);
+    c2c_axis(a, (long)nz * nx, ny, nx, base_y, geo, sign);
+    c2c_axis(a, (long)ny * nx, nz, (long)ny * nx, base_z, geo, sign);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Wavenumbers, masks, projection                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Index -> integer wavenumber: p < n/2 -> p, else p - n (the Nyquist index
+ * n/2 maps to -n/2 on the full axes; on the half x axis indices are 0..n/2). */
+static int wn(int p, int n) { return p < n / 2 ? p : p - n; }
+
+/* Dealiasing mask D(k).  kcut < 0: keep everything.  sphere = 0: cube
+ * max(|kx|,|ky|,|kz|) <= kcut; sphere = 1: |k|^2 <= kcut^2.                 */
+static int kept(int kx, int ky, int kz, int kcut, int sphere)
+{
+    if (kcut < 0) return 1;
+    if (sphere) return (long)kx * kx + (long)ky * ky + (long)kz * kz <= (long)kcut * kcut;
+    return abs(kx) <= kcut && abs(ky) <= kcut && abs(kz) <= kcut;
+}
+
+#define NH(n) ((long)(n) * (n) * ((n) / 2 + 1))
+
+/* Spectral layout: component c, mode (kz, ky, kx) at c*NH + (kz*n + ky)*(n/2+1) + kx. */
+#define IDX(n, z, y, x) (((long)(z) * (n) + (y)) * ((n) / 2 + 1) + (x))
+
+/* i k x v for a spectral vector field (3 components). */
+static void spectral_curl(int n, const cplx *v, cplx *out)
+{
+    long nh = NH(n);
+    int nxh = n / 2 + 1;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < nxh; ++x) {
+                long i = IDX(n, z, y, x);
+                double kx = x, ky = wn(y, n), kz = wn(z, n);
+                cplx vx = v[i], vy = v[nh + i], vz = v[2 * nh + i];
+                out[i] = I * (ky * vz - kz * vy);
+                out[nh + i] = I * (kz * vx - kx * vz);
+                out[2 * nh + i] = I * (kx * vy - ky * vx);
+            }
+}
+
+/* Pointwise cross product c = a x b of physical fields (3 components each),
+ * accumulated into c when acc != 0. */
+static void cross(long np, const double *a, const double *b, double *c, int acc)
+{
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < np; ++i) {
+        double ax = a[i], ay = a[np + i], az = a[2 * np + i];
+        double bx = b[i], by = b[np + i], bz = b[2 * np + i];
+        double cx = ay * bz - az * by, cy = az * bx - ax * bz, cz = ax * by - ay * bx;
+        if (acc) { c[i] += cx; c[np + i] += cy; c[2 * np + i] += cz; }
+        else     { c[i]  = cx; c[np + i]  = cy; c[2 * np + i]  = cz; }
+    }
+}
+
+static void c2r_vec(int n, const cplx *v, double *out)
+{
+    long np = (long)n * n * n, nh = NH(n);
+    for (int c = 0; c < 3; ++c) ora_c2r3(n, n, n, (const double *)(v + c * nh), out + c * np);
+}
+static void r2c_vec(int n, const double *in, cplx *out)
+{
+    long np = (long)n * n * n, nh = NH(n);
+    for (int c = 0; c < 3; ++c) ora_r2c3(n, n, n, in + c * np, (double *)(out + c * nh));
+}
+
+/* out = D(k) P(k) v  (P = I - k k^T / |k|^2, P(0) = 0), optionally + f. */
+static void dealias_project(int n, cplx *v, const cplx *f, int kcut, int sphere)
+{
+    long nh = NH(n);
+    int nxh = n / 2 + 1;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < nxh; ++x) {
+                long i = IDX(n, z, y, x);
+                int ikx = x, iky = wn(y, n), ikz = wn(z, n);
+                double kx = ikx, ky = iky, kz = ikz, k2 = kx * kx + ky * ky + kz * kz;
+                cplx vx = v[i], vy = v[nh + i], vz = v[2 * nh + i];
+                if (!kept(ikx, iky, ikz, kcut, sphere) || k2 == 0.0) {
+                    vx = vy = vz = 0;
+                } else {
+                    cplx kv = (kx * vx + ky * vy + kz * vz) / k2;
+                    vx -= kx * kv; vy -= ky * kv; vz -= kz * kv;
+                }
+                if (f) { vx += f[i]; vy += f[nh + i]; vz += f[2 * nh + i]; }
+                v[i] = vx; v[nh + i] = vy; v[2 * nh + i] = vz;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Right-hand sides                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Navier-Stokes nonlinear operator, rotational form:
+ *   N(u) = D P F[u x w] + f,  w = curl u computed spectrally as i k x uhat.
+ * uhat, fhat, out: [3][n][n][n/2+1] complex.  fhat may be NULL.            */
+void ora_ns_rhs(int n, int kcut, int sphere, const double *uhat, const double *fhat, double *out)
+{
+    long nh = NH(n), np = (long)n * n * n;
+    const cplx *u = (const cplx *)uhat;
+    cplx *w = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nh);
+    double *ur = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    double *wr = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    double *nr = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    spectral_curl(n, u, w);
+    c2r_vec(n, u, ur);
+    c2r_vec(n, w, wr);
+    cross(np, ur, wr, nr, 0);
+    r2c_vec(n, nr, (cplx *)out);
+    dealias_project(n, (cplx *)out, (const cplx *)fhat, kcut, sphere);
+    free(w); free(ur); free(wr); free(nr);
+}
+
+/* MHD nonlinear operators (eq. uMHD, eq. bMHD in rotational form):
+ *   N_u = D P F[u x w + j x b],   N_b = D (i k x F[u x b]),
+ * with w = i k x uhat and j = i k x bhat.                                   */
+void ora_mhd_rhs(int n, int kcut, int sphere, const double *uhat, const double *bhat,
+                 double *out_u, double *out_b)
+{
+    long nh = NH(n), np = (long)n * n * n;
+    const cplx *u = (const cplx *)uhat, *b = (const cplx *)bhat;
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nh);
+    double *ur = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    double *br = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    double *qr = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    double *nr = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    c2r_vec(n, u, ur);
+    c2r_vec(n, b, br);
+    spectral_curl(n, u, tmp);
+    c2r_vec(n, tmp, qr);           /* w */
+    cross(np, ur, qr, nr, 0);      /* u x w */
+    spectral_curl(n, b, tmp);
+    c2r_vec(n, tmp, qr);           /* j */
+    cross(np, qr, br, nr, 1);      /* + j x b */
+    r2c_vec(n, nr, (cplx *)out_u);
+    dealias_project(n, (cplx *)out_u, NULL, kcut, sphere);
+    cross(np, ur, br, nr, 0);      /* u x b */
+    r2c_vec(n, nr, tmp);
+    spectral_curl(n, tmp, (cplx *)out_b);
+    /* D only (the curl is already solenoidal) */
+    int nxh = n / 2 + 1;
+    cplx *ob = (cplx *)out_b;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < nxh; ++x)
+                if (!kept(x, wn(y, n), wn(z, n), kcut, sphere)) {
+                    long i = IDX(n, z, y, x);
+                    ob[i] = ob[nh + i] = ob[2 * nh + i] = 0;
+                }
+    free(tmp); free(ur); free(br); free(qr); free(nr);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time stepping: Lawson integrating factor + explicit Runge-Kutta            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int n;
+    int solver;      /* 0 = Navier-Stokes, 1 = MHD */
+    int rk_order;    /* 2 (Heun) or 4 (classical) */
+    int kcut;        /* dealias cutoff K (< 0: none) */
+    int sphere;      /* 0 = cube truncation, 1 = sphere */
+    int linear_only; /* 1: nonlinear operator replaced by zero */
+    double nu, eta, dt;
+} ora_params;
+
+/* Evaluate the nonlinear operator(s) for the state (u, b) into (ku, kb). */
+static void eval_rhs(const ora_params *p, const cplx *u, const cplx *b, const cplx *f,
+                     cplx *ku, cplx *kb)
+{
+    long nh = NH(p->n);
+    if (p->linear_only) {
+        memset(ku, 0, sizeof(cplx) * 3 * (size_t)nh);
+        if (p->solver == 1) memset(kb, 0, sizeof(cplx) * 3 * (size_t)nh);
+        return;
+    }
+    if (p->solver == 0)
+        ora_ns_rhs(p->n, p->kcut, p->sphere, (const double *)u, (const double *)f, (double *)ku);
+    else
+        ora_mhd_rhs(p->n, p->kcut, p->sphere, (const double *)u, (const double *)b,
+                    (double *)ku, (double *)kb);
+}
+
+/* Integrating factor per mode: E(k) = exp(-visc |k|^2 h / 2). */
+static void if_table(int n, double visc, double h, double *E)
+{
+    int nxh = n / 2 + 1;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < nxh; ++x) {
+                double kx = x, ky = wn(y, n), kz = wn(z, n);
+                double k2 = kx * kx + ky * ky + kz * kz;
+                E[IDX(n, z, y, x)] = exp(-visc * k2 * h * 0.5);
+            }
+}
+
+/* One Lawson step for one field group given the already evaluated stages is
+ * not separable from the others (the operator couples u and b), so the step
+ * below runs the stage loop over all fields together.  Stage formulas:
+ *   RK2 (Heun):  k1 = N(u);  k2 = N(E^2 (u + h k1));
+ *                u+ = E^2 u + h/2 (E^2 k1 + k2)
+ *   RK4:         k1 = N(u);  k2 = N(E (u + h/2 k1));  k3 = N(E u + h/2 k2);
+ *                k4 = N(E^2 u + h E k3);
+ *                u+ = E^2 u + h/6 (E^2 k1 + 2 E (k2 + k3) + k4)              */
+int ora_step(const ora_params *p, double *uhat, double *bhat, const double *fhat, int nsteps)
+{
+    int n = p->n, mhd = p->solver == 1;
+    long nh = NH(n), tot = 3 * nh;
+    int nf = mhd ? 2 : 1;               /* field groups: u (and b) */
+    double h = p->dt;
+    cplx *st[2] = {(cplx *)uhat, mhd ? (cplx *)bhat : NULL};
+    double *E[2];
+    cplx *k1[2], *k2[2], *k3[2], *k4[2], *v[2];
+    for (int g = 0; g < nf; ++g) {
+        E[g] = (double *)malloc(sizeof(double) * (size_t)nh);
+        if_table(n, g == 0 ? p->nu : p->eta, h, E[g]);
+        k1[g] = (cplx *)malloc(sizeof(cplx) * (size_t)tot);
+        k2[g] = (cplx *)malloc(sizeof(cplx) * (size_t)tot);
+        k3[g] = (cplx *)malloc(sizeof(cplx) * (size_t)tot);
+        k4[g] = (cplx *)malloc(sizeof(cplx) * (size_t)tot);
+        v[g] = (cplx *)malloc(sizeof(cplx) * (size_t)tot);
+    }
+    if (!mhd) { k1[1] = k2[1] = k3[1] = k4[1] = v[1] = NULL; }
+    const cplx *f = (const cplx *)fhat;
+
+    for (int s = 0; s < nsteps; ++s) {
+        if (p->rk_order == 2) {
+            eval_rhs(p, st[0], st[1], f, k1[0], k1[1]);
+            for (int g = 0; g < nf; ++g)
+#pragma omp parallel for schedule(static)
+                for (long i = 0; i < tot; ++i) {
+                    double e2 = E[g][i % nh] * E[g][i % nh];
+                    v[g][i] = e2 * (st[g][i] + h * k1[g][i]);
+                }
+            eval_rhs(p, v[0], v[1], f, k2[0], k2[1]);
+            for (int g = 0; g < nf; ++g)
+#pragma omp parallel for schedule(static)
+                for (long i = 0; i < tot; ++i) {
+                    double e2 = E[g][i % nh] * E[g][i % nh];
+                    st[g][i] = e2 * st[g][i] + 0.5 * h * (e2 * k1[g][i] + k2[g][i]);
+                }
+        } else {
+            eval_rhs(p, st[0], st[1], f, k1[0], k1[1]);
+            for (int g = 0; g < nf; ++g)
+#pragma omp parallel for schedule(static)
+                for (long i = 0; i < tot; ++i)
+                    v[g][i] = E[g][i % nh] * (st[g][i] + 0.5 * h * k1[g][i]);
+            eval_rhs(p, v[0], v[1], f, k2[0], k2[1]);
+            for (int g = 0; g < nf; ++g)
+#pragma omp parallel for schedule(static)
+                for (long i = 0; i < tot; ++i)
+                    v[g][i] = E[g][i % nh] * st[g][i] + 0.5 * h * k2[g][i];
+            eval_rhs(p, v[0], v[1], f, k3[0], k3[1]);
+            for (int g = 0; g < nf; ++g)
+#pragma omp parallel for schedule(static)
+                for (long i = 0; i < tot; ++i) {
+                    double e = E[g][i % nh];
+                    v[g][i] = e * e * st[g][i] + h * e * k3[g][i];
+                }
+            eval_rhs(p, v[0], v[1], f, k4[0], k4[1]);
+            for (int g = 0; g < nf; ++g)
+#pragma omp parallel for schedule(static)
+                for (long i = 0; i < tot; ++i) {
+                    double e = E[g][i % nh];
+                    st[g][i] = e * e * st[g][i]
+                             + h / 6.0 * (e * e * k1[g][i] + 2.0 * e * (k2[g][i] + k3[g][i]) + k4[g][i]);
+                }
+        }
+    }
+    for (int g = 0; g < nf; ++g) {
+        free(E[g]); free(k1[g]); free(k2[g]); free(k3[g]); free(k4[g]); free(v[g]);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Weight of a stored half-spectrum mode in sums over the full spectrum:
+ * 1 on the self-conjugate planes kx = 0 and kx = n/2, otherwise 2.          */
+static double hweight(int x, int n) { return (x == 0 || 2 * x == n) ? 1.0 : 2.0; }
+
+/* Pairwise (cascade) summation of an array, the usual way to keep the
+ * rounding error of a long sum at O(log n) ulps.                            */
+static double pairwise(const double *a, long m)
+{
+    if (m <= 16) {
+        double s = 0;
+        for (long i = 0; i < m; ++i) s += a[i];
+        return s;
+    }
+    long h = m / 2;
+    return pairwise(a, h) + pairwise(a + h, m - h);
+}
+
+/* Kinetic (or magnetic) energy E = 1/2 sum_k w |vhat|^2 = <|v|^2>/2. */
+double ora_energy(int n, const double *vhat)
+{
+    long nh = NH(n);
+    int nxh = n / 2 + 1;
+    const cplx *v = (const cplx *)vhat;
+    double *t = (double *)malloc(sizeof(double) * (size_t)nh);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nh; ++i) {
+        int x = (int)(i % nxh);
+        double s = 0;
+        for (int c = 0; c < 3; ++c) {
+            cplx z = v[c * nh + i];
+            s += creal(z) * creal(z) + cimag(z) * cimag(z);
+        }
+        t[i] = 0.5 * hweight(x, n) * s;
+    }
+    double e = pairwise(t, nh);
+    free(t);
+    return e;
+}
+
+/* Shell index n = floor(|k| + 1/2). */
+static int shell_of(long k2) { return (int)floor(sqrt((double)k2) + 0.5); }
+
+/* Shell spectrum E(s) = 1/2 sum_{shell s} w |vhat|^2, s = 0..nshells-1.
+ * Modes beyond the last shell are ignored.                                  */
+void ora_spectrum(int n, const double *vhat, double *Ek, int nshells)
+{
+    long nh = NH(n);
+    int nxh = n / 2 + 1;
+    const cplx *v = (const cplx *)vhat;
+    /* gather per-shell terms, then sum each shell pairwise */
+    long *cnt = (long *)calloc((size_t)nshells, sizeof(long));
+    for (long i = 0; i < nh; ++i) {
+        int x = (int)(i % nxh), y = (int)((i / nxh) % n), z = (int)(i / ((long)nxh * n));
+        long kx = x, ky = wn(y, n), kz = wn(z, n);
+        int s = shell_of(kx * kx + ky * ky + kz * kz);
+        if (s < nshells) cnt[s]++;
+    }
+    double **terms = (double **)malloc(sizeof(double *) * (size_t)nshells);
+    long *fill = (long *)calloc((size_t)nshells, sizeof(long));
+    for (int s = 0; s < nshells; ++s) terms[s] = (double *)malloc(sizeof(double) * (size_t)(cnt[s] + 1));
+    for (long i = 0; i < nh; ++i) {
+        int x = (int)(i % nxh), y = (int)((i / nxh) % n), z = (int)(i / ((long)nxh * n));
+        long kx = x, ky = wn(y, n), kz = wn(z, n);
+        int s = shell_of(kx * kx + ky * ky + kz * kz);
+        if (s >= nshells) continue;
+        double a = 0;
+        for (int c = 0; c < 3; ++c) {
+            cplx q = v[c * nh + i];
+            a += creal(q) * creal(q) + cimag(q) * cimag(q);
+        }
+        terms[s][fill[s]++] = 0.5 * hweight(x, n) * a;
+    }
+    for (int s = 0; s < nshells; ++s) {
+        Ek[s] = pairwise(terms[s], fill[s]);
+        free(terms[s]);
+    }
+    free(terms); free(fill); free(cnt);
+}

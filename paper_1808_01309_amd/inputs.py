@@ -1,0 +1,202 @@
+"""Seeded synthetic inputs shared by the HIP path and the oracle.
+
+This module holds input recipes only (initial fields and forcing, given
+directly by their Fourier coefficients or by their physical-space formula); it
+contains no transform, operator, time step or diagnostic of the method.
+
+Spectral arrays use the library layout: complex [3][n][n][n//2+1] (kz, ky, kx;
+kx fastest), coefficients normalised so that u(x) = sum_k uhat(k) exp(i k.x).
+Index p on a full axis is the wavenumber p for p < n/2 and p - n otherwise.
+
+Random numbers come from SplitMix64 (Steele, Lea & Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014) used as a counter-based
+generator: draw j of mode (kx, ky, kz) of field f under seed s is
+mix64(key(s, f, kx, ky, kz) + (j + 1) * GOLDEN), so a field is the same
+whatever order the modes are visited in.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def kcut_23(n: int) -> int:
+    """Cube-truncation cutoff K = ceil(n/3) - 1 (the largest K with 3K < n)."""
+    return -(-n // 3) - 1
+
+
+def _mix64(z):
+    z = (z ^ (z >> np.uint64(30))) * _M1
+    z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def _key(seed, field, kx, ky, kz):
+    m = np.uint64(0x100000001B3)  # odd multiplier (FNV prime) to chain the counters
+    k = np.uint64(seed) * m + np.uint64(field)
+    for c in (kx, ky, kz):
+        k = k * m + (np.asarray(c, np.int64).astype(np.uint64) & np.uint64(0xFFFF))
+    return k
+
+
+def uniform(seed, field, kx, ky, kz, j):
+    """Counter-based uniform draw in [0, 1) (53-bit)."""
+    with np.errstate(over="ignore"):
+        z = _mix64(_key(seed, field, kx, ky, kz) + np.uint64(j + 1) * GOLDEN)
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def wavenumbers(n):
+    """Integer wavenumbers of the stored half spectrum, shaped for broadcasting
+    against [n][n][n//2+1] (kz, ky, kx)."""
+    full = np.where(np.arange(n) < n // 2, np.arange(n), np.arange(n) - n)
+    kz = full[:, None, None]
+    ky = full[None, :, None]
+    kx = np.arange(n // 2 + 1)[None, None, :]
+    return kx, ky, kz
+
+
+def cube_mask(n, kcut=None):
+    if kcut is None:
+        kcut = kcut_23(n)
+    kx, ky, kz = wavenumbers(n)
+    return (np.abs(kx) <= kcut) & (np.abs(ky) <= kcut) & (np.abs(kz) <= kcut)
+
+
+def spectrum_c2(k):
+    """E(k) proportional to k^4 exp(-2 (k/4)^2) (peak at k = 4)."""
+    return k ** 4 * np.exp(-2.0 * (k / 4.0) ** 2)
+
+
+def spectrum_c3(k):
+    """E(k) proportional to k^2 exp(-(k/3)^2)."""
+    return k ** 2 * np.exp(-((k / 3.0) ** 2))
+
+
+def flat_shells(lo, hi):
+    """Flat amplitude on shells lo <= floor(|k| + 1/2) <= hi (forcing recipe)."""
+    def e(k):
+        s = np.floor(k + 0.5)
+        return np.where((s >= lo) & (s <= hi), 4.0 * np.pi * k ** 2, 0.0)
+    return e
+
+
+def random_solenoidal(n, seed, field=0, spectrum=spectrum_c2, energy=1.0, kcut=None,
+                      dtype=np.complex128):
+    """Random-phase solenoidal field in the library's spectral layout.
+
+    For every stored mode k != 0 inside the cube |k_i| <= kcut:
+        uhat = A(|k|) (exp(i t1) cos(phi) e1 + exp(i t2) sin(phi) e2),
+        e1 = k x z / |k x z|  (x if k is parallel to z),  e2 = k x e1 / |k x e1|,
+        A = sqrt(E(|k|) / (4 pi |k|^2)),
+    with t1, t2, phi uniform in [0, 2 pi) from the counter-based generator.
+    On the kx = 0 plane the half with ky > 0 (or ky = 0, kz > 0) is drawn and
+    the other half is its complex conjugate, so the field is real.  |uhat| = A
+    whatever the phases, so the amplitudes are rescaled to the requested
+    energy 1/2 sum_k w |uhat|^2 (w = 1 on kx = 0, else 2) before the phases are
+    applied.
+    """
+    if kcut is None:
+        kcut = kcut_23(n)
+    nxh = n // 2 + 1
+    out = np.zeros((3, n, n, nxh), dtype)
+    ks = np.arange(-kcut, kcut + 1)
+    kz, ky, kx = np.meshgrid(ks, ks, np.arange(0, min(kcut, n // 2) + 1), indexing="ij")
+    kz, ky, kx = kz.ravel(), ky.ravel(), kx.ravel()
+    canon = (kx > 0) | ((kx == 0) & ((ky > 0) | ((ky == 0) & (kz > 0))))
+    kx, ky, kz = kx[canon], ky[canon], kz[canon]
+    k2 = (kx * kx + ky * ky + kz * kz).astype(np.float64)
+    kmag = np.sqrt(k2)
+    amp2 = spectrum(kmag) / (4.0 * np.pi * k2)
+    # a canonical kx > 0 mode has weight 2; a canonical kx = 0 mode stands for
+    # itself and its mirror, weight 1 each: every canonical mode counts twice
+    e_tot = 0.5 * np.sum(2.0 * amp2)
+    amp = np.sqrt(amp2 * (energy / e_tot)) if e_tot > 0 else np.zeros_like(amp2)
+    t1 = 2.0 * np.pi * uniform(seed, field, kx, ky, kz, 0)
+    t2 = 2.0 * np.pi * uniform(seed, field, kx, ky, kz, 1)
+    ph = 2.0 * np.pi * uniform(seed, field, kx, ky, kz, 2)
+    kvec = np.stack([kx, ky, kz]).astype(np.float64)
+    # e1 = k x zhat = (ky, -kx, 0), or xhat when k is parallel to zhat
+    e1 = np.stack([kvec[1], -kvec[0], np.zeros_like(kmag)])
+    par = (kx == 0) & (ky == 0)
+    e1[:, par] = np.array([1.0, 0.0, 0.0])[:, None]
+    e1 /= np.linalg.norm(e1, axis=0)
+    e2 = np.cross(kvec.T, e1.T).T
+    e2 /= np.linalg.norm(e2, axis=0)
+    coef = (np.exp(1j * t1) * np.cos(ph))[None] * e1 + (np.exp(1j * t2) * np.sin(ph))[None] * e2
+    coef *= amp[None]
+    iy = np.mod(ky, n)
+    iz = np.mod(kz, n)
+    for c in range(3):
+        out[c, iz, iy, kx] = coef[c]
+    m0 = kx == 0
+    for c in range(3):
+        out[c, np.mod(-kz[m0], n), np.mod(-ky[m0], n), 0] = np.conj(coef[c][m0])
+    return out
+
+
+def forcing_shells(n, seed, lo=2, hi=3, energy=1.0, kcut=None, dtype=np.complex128):
+    """Constant solenoidal random-phase forcing on shells lo..hi (seed + 1)."""
+    return random_solenoidal(n, seed + 1, field=7, spectrum=flat_shells(lo, hi),
+                             energy=energy, kcut=kcut, dtype=dtype)
+
+
+# ------------------------------------------------------------ analytic fields
+def taylor_green_phys(n, dtype=np.float64):
+    """u = (sin x cos y cos z, -cos x sin y cos z, 0) on the grid x_j = 2 pi j / n."""
+    x = 2.0 * np.pi * np.arange(n) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    u = np.stack([np.sin(X) * np.cos(Y) * np.cos(Z), -np.cos(X) * np.sin(Y) * np.cos(Z),
+                  np.zeros_like(X)])
+    return u.astype(dtype)
+
+
+def taylor_green_spec(n, dtype=np.complex128):
+    """Fourier coefficients of the Taylor-Green field: on kx = 1,
+    uhat_x(1, sy, sz) = -i/8 and uhat_y(1, sy, sz) = i sy / 8 for sy, sz = +-1."""
+    out = np.zeros((3, n, n, n // 2 + 1), dtype)
+    for sy in (1, -1):
+        for sz in (1, -1):
+            out[0, sz % n, sy % n, 1] = -1j / 8
+            out[1, sz % n, sy % n, 1] = 1j * sy / 8
+    return out
+
+
+def abc_spec(n, A=1.0, B=1.0, C=1.0, dtype=np.complex128):
+    """Arnold-Beltrami-Childress flow u = (A sin z + C cos y, B sin x + A cos z,
+    C sin y + B cos x) by its Fourier coefficients (curl u = u)."""
+    out = np.zeros((3, n, n, n // 2 + 1), dtype)
+    # sin z = (e^{iz} - e^{-iz}) / 2i ; cos y = (e^{iy} + e^{-iy}) / 2 (kx = 0 plane: both)
+    out[0, 1, 0, 0] += A / 2j
+    out[0, n - 1, 0, 0] += -A / 2j
+    out[0, 0, 1, 0] += C / 2
+    out[0, 0, n - 1, 0] += C / 2
+    out[1, 0, 0, 1] += B / 2j            # sin x, kx = 1 only in the half spectrum
+    out[1, 1, 0, 0] += A / 2
+    out[1, n - 1, 0, 0] += A / 2
+    out[2, 0, 1, 0] += C / 2j
+    out[2, 0, n - 1, 0] += -C / 2j
+    out[2, 0, 0, 1] += B / 2             # cos x
+    return out
+
+
+def shear_wave_spec(n, k=1, amp=1.0, dtype=np.complex128):
+    """u = amp sin(k z) xhat."""
+    out = np.zeros((3, n, n, n // 2 + 1), dtype)
+    out[0, k % n, 0, 0] = amp / 2j
+    out[0, (-k) % n, 0, 0] = -amp / 2j
+    return out
+
+
+def alfven_spec(n, k=1, amp=0.1, b0=1.0, dtype=np.complex128):
+    """Alfven wave on a mean field b0 zhat: u = amp cos(k z) xhat,
+    b = b0 zhat - amp cos(k z) xhat.  Returns (uhat, bhat)."""
+    u = np.zeros((3, n, n, n // 2 + 1), dtype)
+    u[0, k % n, 0, 0] = amp / 2
+    u[0, (-k) % n, 0, 0] = amp / 2
+    b = -u.copy()
+    b[2, 0, 0, 0] = b0
+    return u, b
