@@ -1,0 +1,215 @@
+"""Benchmark: ms per RK4 step and per-pass HBM bandwidth of the pseudospectral
+Navier-Stokes hot path at 512^3, FP32 (headline) and FP64, on one GPU.
+
+Workload (Navier-Stokes 512^3): solenoidal random-phase initial velocity with
+E(k) ~ k^4 exp(-2 (k/4)^2), seed 1, unit energy; constant random-phase
+forcing on shells 2..3 (seed 2, unit forcing energy); nu = 2e-3; classical
+RK4 with the viscous integrating factor; dt = 5e-4.  The state is resident in
+HBM before the timed region; each timed step is one full pass of the hot path
+(4 right-hand sides of 5 kernels each, with the RK update fused).
+
+Prints one JSON line.  Also reported: the standalone 3D r2c / c2r transforms
+of 3 fields at 512^3 per pass in GB/s, the roofline of the dominant kernel
+(algorithmic bytes per launch / HIP-event-timed launch duration), and the FP64
+CPU oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "ms/RK step + FFT HBM GB/s at 512^3, FP32 vs FP64; surrogate speed-up @1e-2 err"
+KINDS = ["zinv", "yinv", "xpass", "yfwd", "zfwd"]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fft", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_bytes(n, esz, rk):
+    """Algorithmic HBM bytes per launch of each solver kernel (Navier-Stokes):
+    every array element a pass must read or write, once."""
+    K = -(-n // 3) - 1
+    M, nxk = 2 * K + 1, K + 1
+    sc, sa, sb = nxk * M * M, nxk * M * n, nxk * n * n
+    rk_arrays = 13.0 / 4.0 if rk == 4 else 5.0 / 2.0  # state-sized arrays touched per stage update
+    return {
+        "zinv": (3 * sc + 6 * sa) * esz,
+        "yinv": (6 * sa + 6 * sb) * esz,
+        "xpass": (6 * sb + 3 * sb) * esz,
+        "yfwd": (3 * sb + 3 * sa) * esz,
+        "zfwd": (3 * sa + rk_arrays * 3 * sc) * esz,
+    }
+
+
+def fft_bytes(n, nf, esz_c):
+    """Algorithmic bytes per pass of the standalone unpruned 3D transforms."""
+    nxh = n // 2 + 1
+    real = nf * n ** 3 * (esz_c // 2)
+    cplx = nf * n * n * nxh * esz_c
+    return {"fftx": real + cplx, "ffty": 2 * cplx, "fftz": 2 * cplx}
+
+
+def run_solver(pst, torch, I, n, prec, steps, warmup):
+    plan = pst.Plan(n, precision=prec, rk_order=4, nu=2e-3, dt=5e-4, timers=True)
+    cdt = np.complex128 if prec == "fp64" else np.complex64
+    plan.set_state(I.random_solenoidal(n, 1, dtype=cdt))
+    plan.set_forcing(I.forcing_shells(n, 1, dtype=cdt))
+    plan.step(warmup)
+    torch.cuda.synchronize()
+    plan.timers(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = plan.timers(reset=True)
+    e = plan.energy()[0]
+    info = plan.query()
+    plan.close()
+    return (t1 - t0) * 1e3 / steps, tm, e, info
+
+
+def run_fft(pst, torch, n, prec, reps=5, nf=3):
+    plan = pst.Plan(n, precision=prec, timers=True)
+    rt = torch.float64 if prec == "fp64" else torch.float32
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    x = torch.randn((nf, n, n, n), dtype=rt, device="cuda")
+    y = torch.empty((nf, n, n, n // 2 + 1), dtype=ct, device="cuda")
+    z = torch.empty_like(x)
+    plan.fft_r2c(x, y, nf)
+    plan.fft_c2r(y, z, nf)
+    torch.cuda.synchronize()
+    plan.timers(reset=True)
+    res = {}
+    for name, fn in (("r2c", lambda: plan.fft_r2c(x, y, nf)), ("c2r", lambda: plan.fft_c2r(y, z, nf))):
+        for _ in range(reps):
+            fn()
+        tm = plan.timers(reset=True)
+        res[name] = {k: tm[k][0] / max(tm[k][1], 1) for k in ("fftx", "ffty", "fftz")}
+    plan.close()
+    del x, y, z
+    torch.cuda.empty_cache()
+    return res
+
+
+def traffic_from_profiles(kernel, n, prec):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, valid
+    only while the kernel sources are unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_n{n}_{prec}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha") != kernel_source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1808_01309_amd", "csrc")
+    for f in ("fft_engine.h", "kernels.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(n):
+    """The FP64 oracle (untuned) on this host: one Navier-Stokes right-hand side
+    at n^3 (one of the four stages of an RK4 step), scaled x4 to ms per step."""
+    import oracle as O
+    from paper_1808_01309_amd import inputs as I
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    u = I.random_solenoidal(n, 1)
+    f = I.forcing_shells(n, 1)
+    t0 = time.perf_counter()
+    O.ns_rhs(u, f)
+    dt = time.perf_counter() - t0
+    return {"value": dt * 4e3, "unit": "ms/RK4 step", "cores": threads, "kind": "oracle",
+            "sample": f"one FP64 right-hand side (9 textbook 3D FFTs + products + projection) at "
+                      f"{n}^3 took {dt:.2f} s; x4 stages per RK4 step (stage updates excluded)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus_requested": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_1808_01309_amd import inputs as I
+    from paper_1808_01309_amd import pst
+
+    n = a.n
+    print(f"[bench] n={n} fp32 solver: warmup {a.warmup}, timed {a.steps}", file=sys.stderr, flush=True)
+    ms32, tm32, e32, info = run_solver(pst, torch, I, n, "fp32", a.steps, a.warmup)
+    out_extra = {"fp32": {"ms_per_step": ms32, "energy_end": e32}}
+    per32 = {k: tm32[k][0] / max(tm32[k][1], 1) for k in KINDS}
+    kb32 = kernel_bytes(n, 8, 4)
+    out_extra["fp32"]["kernels"] = {k: {"ms": per32[k], "GB_s": kb32[k] / per32[k] / 1e6,
+                                        "launches": tm32[k][1]} for k in KINDS}
+    step_bytes32 = 4 * sum(kb32.values())
+    out_extra["fp32"]["effective_GB_s"] = step_bytes32 / ms32 / 1e6
+    out_extra["fp32"]["algorithmic_GB_per_step"] = step_bytes32 / 1e9
+    if not a.no_fp64:
+        print(f"[bench] n={n} fp64 solver", file=sys.stderr, flush=True)
+        ms64, tm64, e64, _ = run_solver(pst, torch, I, n, "fp64", a.steps, a.warmup)
+        per64 = {k: tm64[k][0] / max(tm64[k][1], 1) for k in KINDS}
+        kb64 = kernel_bytes(n, 16, 4)
+        out_extra["fp64"] = {"ms_per_step": ms64, "energy_end": e64,
+                             "kernels": {k: {"ms": per64[k], "GB_s": kb64[k] / per64[k] / 1e6,
+                                             "launches": tm64[k][1]} for k in KINDS},
+                             "effective_GB_s": 4 * sum(kb64.values()) / ms64 / 1e6}
+    if not a.no_fft:
+        print(f"[bench] n={n} standalone FFTs", file=sys.stderr, flush=True)
+        ffts = {}
+        for prec, esz in (("fp32", 8), ("fp64", 16)):
+            if prec == "fp64" and a.no_fp64:
+                continue
+            r = run_fft(pst, torch, n, prec)
+            fb = fft_bytes(n, 3, esz)
+            ffts[prec] = {d: {k: {"ms": r[d][k], "GB_s": fb[k] / r[d][k] / 1e6} for k in fb} for d in r}
+        out_extra["fft_3fields"] = ffts
+    # dominant kernel of the headline (FP32) step
+    dom = max(KINDS, key=lambda k: tm32[k][0])
+    ach = kb32[dom] / per32[dom] / 1e6
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic_from_profiles(dom, n, "fp32"),
+            "algorithmic_bytes_per_launch": kb32[dom], "avg_launch_ms": per32[dom]}
+    cpu = None
+    if not a.no_cpu:
+        print(f"[bench] cpu baseline (oracle, {n}^3 FP64 rhs)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(n)
+    line = {
+        "metric": METRIC, "value": round(ms32, 4), "unit": "ms/RK4 step", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms32, 4), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Navier-Stokes {n}^3 periodic, RK4 dt=5e-4, nu=2e-3, random-phase "
+                               f"E(k)~k^4 exp(-2(k/4)^2) unit energy, shell 2-3 forcing, 2/3-rule cube "
+                               f"dealiasing", "n": n, "precision": "fp32", "rk_order": 4,
+                   "radices": info["radices"], "tile_lines": info["tile_lines"]},
+        "roofline": roof, "cpu_baseline": cpu, "extra": out_extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * pst.h -- C ABI of the MI355X-native pseudospectral turbulence hot path.
+ *
+ * The library evaluates and time-steps the incompressible Navier-Stokes
+ * equations (the paper's eq. mom + eq. divv with theta = 0) and, as a second
+ * solver, incompressible MHD (eq. uMHD, eq. bMHD) on a periodic n^3 grid of
+ * [0, 2 pi)^3 with the Fourier-Galerkin pseudospectral method of Sec. 2:
+ * nonlinear terms are formed in physical space between backward and forward
+ * 3D transforms, pressure is applied by projecting onto divergence-free
+ * fields, and an explicit Runge-Kutta scheme advances the Fourier
+ * coefficients.  Every step runs in hand-written HIP kernels for gfx950.
+ *
+ * Plans follow the create / execute / destroy life cycle of the paper's
+ * transform plans (Sec. 3.2): a plan owns every device buffer it allocates
+ * and borrows the caller's HIP stream.  All functions return a pst_status;
+ * 0 (PST_OK) is success, as for the runtime return codes the paper binds
+ * (Sec. 3.1).  Nothing throws or aborts across this interface.  Errors are
+ * sticky per plan: pst_last_error() returns the message of the last failure.
+ * Plans are not thread-safe; use one plan per host thread.
+ *
+ * Conventions
+ *  - Transform (eq. fftsum): forward sign -, scaled by 1/n^3 so that
+ *    u(x) = sum_k uhat(k) exp(i k.x); backward sign +, unscaled.
+ *  - Physical layout:  real    [ncomp][n][n][n]       (z, y, x; x fastest).
+ *  - Spectral layout:  complex [ncomp][n][n][n/2+1]   (kz, ky, kx; kx fastest),
+ *    interleaved (re, im).  Index p on a full axis is wavenumber p for p < n/2,
+ *    p - n otherwise; kx runs over 0..n/2 (Hermitian half, Sec. 2).
+ *  - Element type follows the plan precision: float (PST_FP32) or double
+ *    (PST_FP64).  Diagnostics are always double.
+ *  - Dealiasing: cube truncation max(|kx|,|ky|,|kz|) <= K, K = ceil(n/3) - 1
+ *    (the largest K with 3K < n, alias-free for quadratic products).  The
+ *    state only ever holds these modes.
+ *  - Time stepping: Lawson integrating factor E = exp(-nu |k|^2 h / 2)
+ *    (eta for b) with Heun RK2 or classical RK4.
+ *  - "device" pointers are HIP device allocations on the current device;
+ *    "host" pointers are ordinary host memory.
+ *  - Stream-ordered calls only enqueue work on the plan's stream; synchronous
+ *    calls wait for it.
+ */
+#ifndef PST_H
+#define PST_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PST_OK = 0,
+    PST_ERR_INVALID_ARG = 1,   /* bad pointer, size, enum or state */
+    PST_ERR_UNSUPPORTED_N = 2, /* n not in the supported set */
+    PST_ERR_OOM = 3,           /* device allocation failed */
+    PST_ERR_HIP = 4,           /* a HIP runtime call failed */
+    PST_ERR_NONFINITE = 5,     /* a diagnostic found NaN or Inf */
+    PST_ERR_UNSUPPORTED = 6    /* option not implemented for this plan */
+} pst_status;
+
+typedef enum { PST_NS = 0, PST_MHD = 1 } pst_solver;
+typedef enum { PST_FP32 = 0, PST_FP64 = 1 } pst_precision;
+typedef enum { PST_DEALIAS_CUBE = 0 } pst_dealias;
+typedef enum { PST_FIELD_U = 0, PST_FIELD_B = 1 } pst_field;
+typedef enum { PST_SPACE_PHYS = 0, PST_SPACE_SPEC = 1 } pst_space;
+typedef enum { PST_MEM_HOST = 0, PST_MEM_DEVICE = 1 } pst_mem;
+
+enum {
+    PST_FLAG_LINEAR_ONLY = 1u, /* nonlinear operator replaced by 0 (tests of the integrating factor) */
+    PST_FLAG_TIMERS = 2u       /* record HIP events around every kernel (see pst_timer_read) */
+};
+
+typedef struct {
+    int n;            /* grid points per direction; see pst_supported_n() */
+    int solver;       /* pst_solver */
+    int precision;    /* pst_precision */
+    int rk_order;     /* 2 (Heun) or 4 (classical) */
+    double nu;        /* kinematic viscosity */
+    double eta;       /* magnetic diffusivity (MHD) */
+    double dt;        /* time step h */
+    int dealias;      /* pst_dealias */
+    unsigned flags;   /* PST_FLAG_* */
+} pst_params;
+
+typedef struct {
+    int n, kcut;              /* grid size and dealias cutoff K */
+    int ncomp;                /* state components: 3 (NS) or 6 (MHD) */
+    size_t modes_per_comp;    /* stored modes per component: (K+1)(2K+1)^2 */
+    size_t workspace_bytes;   /* device bytes owned by the plan */
+    int radices[4];           /* FFT radix schedule of the n-point transforms (0-terminated) */
+    int tile_lines;           /* lines per workgroup in the strided passes */
+    long long steps_done;     /* time steps taken since the last set_state */
+} pst_info;
+
+/* Kernel kinds reported by pst_timer_read (PST_FLAG_TIMERS). */
+typedef enum {
+    PST_K_ZINV = 0,   /* backward z transform + spectral curl */
+    PST_K_YINV = 1,   /* backward y transform */
+    PST_K_XPASS = 2,  /* fused backward x (c2r), cross products, forward x (r2c) */
+    PST_K_YFWD = 3,   /* forward y transform */
+    PST_K_ZFWD = 4,   /* forward z transform + projection + forcing + RK update */
+    PST_K_FFTX = 5,   /* standalone transforms: x (r2c / c2r) */
+    PST_K_FFTY = 6,   /* standalone transforms: y */
+    PST_K_FFTZ = 7,   /* standalone transforms: z */
+    PST_K_OTHER = 8,  /* gathers, scatters, reductions */
+    PST_K_COUNT = 9
+} pst_kernel_kind;
+
+typedef struct pst_plan pst_plan;
+
+/* Text of a status code (static storage). */
+const char *pst_status_str(pst_status s);
+
+/* Message of the last failure on this plan ("" if none; plan may be NULL for
+ * failures of pst_plan_create, which are kept per host thread). */
+const char *pst_last_error(const pst_plan *plan);
+
+/* 1 if n is supported by this build, else 0.  Supported n are products of 2
+ * and 3 with a compiled FFT schedule: 16, 24, 32, 48, 64, 96, 128, 256, 512,
+ * 1024. */
+int pst_supported_n(int n);
+
+/* Create a plan (Sec. 3.2, plan creation): validates p, allocates the state,
+ * the pass buffers, FP64-generated twiddle and integrating-factor tables
+ * (rounded once to the plan precision).  hip_stream (hipStream_t, may be NULL
+ * for the null stream) is borrowed and must outlive the plan.  The state
+ * starts at zero.  Errors: INVALID_ARG, UNSUPPORTED_N, UNSUPPORTED, OOM, HIP. */
+pst_status pst_plan_create(const pst_params *p, void *hip_stream, pst_plan **out);
+
+/* Free everything the plan owns (synchronises its stream).  NULL is a no-op. */
+void pst_plan_destroy(pst_plan *plan);
+
+/* Load field u (or b, MHD) from src.  PHYS: real [3][n][n][n]; SPEC: complex
+ * [3][n][n][n/2+1].  The data is copied: modes outside the dealiasing cube
+ * are dropped and the kx = 0 plane is made Hermitian ((X(k) + conj X(-k))/2).
+ * mem says where src lives; a HOST copy is synchronous, a DEVICE copy is
+ * stream-ordered.  Resets the step counter. */
+pst_status pst_set_state(pst_plan *plan, int field, int space, const void *src, int mem);
+
+/* Write field u (or b) to dst in the layout of pst_set_state (all modes
+ * outside the cube are zero).  HOST: synchronous; DEVICE: stream-ordered. */
+pst_status pst_get_state(pst_plan *plan, int field, int space, void *dst, int mem);
+
+/* Constant forcing fhat added to the projected NS nonlinear term, spectral
+ * layout [3][n][n][n/2+1]; it should be solenoidal (it is dealiased, not
+ * projected).  NULL removes the forcing.  NS only.  Synchronous for HOST. */
+pst_status pst_set_forcing(pst_plan *plan, const void *fhat, int mem);
+
+/* Nonlinear right-hand side of the state in state_dev (device, spectral
+ * layout; NS: [3] comps of u, MHD: [6] = u then b), written to rhs_dev (same
+ * layout):  NS  N = D P F[u x w] + f;  MHD  N_u = D P F[u x w + j x b],
+ * N_b = D (i k x F[u x b]).  Viscous terms are excluded.  Stream-ordered.
+ * Does not touch the plan's state. */
+pst_status pst_rhs(pst_plan *plan, const void *state_dev, void *rhs_dev);
+
+/* Advance the plan's state by nsteps integrating-factor RK steps.
+ * Stream-ordered. */
+pst_status pst_step(pst_plan *plan, int nsteps);
+
+/* Energies E = 1/2 <|v|^2> = 1/2 sum_k w |vhat|^2 (w = 1 on kx = 0, else 2)
+ * of u and b (out[1] = 0 for NS), accumulated in double.  Synchronous.
+ * NONFINITE if either is NaN/Inf. */
+pst_status pst_energy(pst_plan *plan, double out[2]);
+
+/* Shell spectrum E(s) = 1/2 sum_{floor(|k|+1/2) = s} w |vhat|^2 for
+ * s = 0..nshells-1 (double).  nshells must be >= floor(sqrt(3) K + 1/2) + 1.
+ * Synchronous. */
+pst_status pst_spectrum(pst_plan *plan, int field, double *Ek, int nshells);
+
+/* Standalone unpruned 3D transforms of nfields fields (device pointers, the
+ * plan's n and precision).  r2c: real [nfields][n][n][n] -> complex
+ * [nfields][n][n][n/2+1], scaled by 1/n^3.  c2r: the inverse, unscaled,
+ * imaginary parts of the self-conjugate points ignored; in is not modified.
+ * in and out must not overlap.  Stream-ordered; c2r uses plan workspace. */
+pst_status pst_fft_r2c(pst_plan *plan, const void *in, void *out, int nfields);
+pst_status pst_fft_c2r(pst_plan *plan, const void *in, void *out, int nfields);
+
+/* Sizes and schedule of the plan. */
+pst_status pst_query(const pst_plan *plan, pst_info *info);
+
+/* With PST_FLAG_TIMERS: synchronise, and return per kernel kind the summed
+ * duration in ms and the launch count since the last reset (arrays of
+ * PST_K_COUNT entries; either may be NULL), then reset if reset != 0.
+ * Durations come from HIP events recorded on the plan's stream around each
+ * launch.  Without the flag: UNSUPPORTED. */
+pst_status pst_timer_read(pst_plan *plan, double *ms, long long *count, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PST_H */

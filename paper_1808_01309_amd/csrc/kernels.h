@@ -1,0 +1,593 @@
+// Pass kernels of the pseudospectral right-hand side and of the standalone
+// 3D transforms, templated on element type T and grid size N.
+//
+// Right-hand side (Sec. 2: products in physical space, projection in
+// spectral space; transform steps as in the slab algorithm of Sec. 2 with the
+// global transpose replaced by on-device strided passes):
+//   zinv   state (kept modes)  -> curl in registers -> backward z  -> A
+//   yinv   A (kept ky rows)    -> backward y                       -> B
+//   xpass  B (kx <= K rows)    -> backward x (c2r), u x w (+ j x b, u x b),
+//                                 forward x (r2c), keep kx <= K    -> C
+//   yfwd   C                   -> forward y, keep kept ky rows     -> D (= A)
+//   zfwd   D                   -> forward z, keep kept kz, 1/n^3, projection
+//                                 (or curl for b), forcing, RK stage update
+// Only modes inside the dealiasing cube are ever read or written, so the
+// transforms are pruned on both ends; physical-space fields never touch HBM.
+#pragma once
+#include "fft_engine.h"
+#include "plan.h"
+
+namespace pst {
+
+// ------------------------------------------------------------ size configs
+// Radix schedule and threads per line for every supported n.
+template <int N> struct NCfg;
+template <> struct NCfg<16>   { using P = Radices<4, 4>;    static constexpr int G = 4; };
+template <> struct NCfg<24>   { using P = Radices<4, 2, 3>; static constexpr int G = 2; };
+template <> struct NCfg<32>   { using P = Radices<8, 4>;    static constexpr int G = 4; };
+template <> struct NCfg<48>   { using P = Radices<4, 4, 3>; static constexpr int G = 4; };
+template <> struct NCfg<64>   { using P = Radices<8, 8>;    static constexpr int G = 8; };
+template <> struct NCfg<96>   { using P = Radices<8, 4, 3>; static constexpr int G = 4; };
+template <> struct NCfg<128>  { using P = Radices<4, 8, 4>; static constexpr int G = 16; };
+template <> struct NCfg<256>  { using P = Radices<4, 8, 8>; static constexpr int G = 32; };
+template <> struct NCfg<512>  { using P = Radices<8, 8, 8>; static constexpr int G = 64; };
+template <> struct NCfg<1024> { using P = Radices<8, 16, 8>; static constexpr int G = 64; };
+
+// Lines per workgroup of the strided passes: 128-byte row segments.
+template <typename T> constexpr int tile_lines() { return sizeof(T) == 4 ? 16 : 8; }
+// The x pass keeps every field of a line in registers until the products are
+// formed: MHD (twice the fields) and n = 1024 (twice the points per thread)
+// each halve the tile so the block stays within the register file.
+template <typename T, bool MHD, int N>
+constexpr int xpass_lines() { return tile_lines<T>() / (MHD ? 2 : 1) / (N >= 1024 ? 2 : 1); }
+constexpr int LINE_BLOCK = 256;
+
+template <typename T>
+struct RkArgs {
+    cx<T>* U;          // u_n (compact)
+    cx<T>* V;          // next stage input
+    cx<T>* Acc;        // accumulator
+    cx<T>* R;          // rhs output (Z_RHS)
+    const T* E[2];     // exp(-visc |k|^2 h / 2) by |k|^2, for u and b
+    const T* E2[2];    // exp(-visc |k|^2 h)
+    T h;
+    const cx<T>* F;    // forcing box or null
+    int kf;
+    int lin_only;
+};
+
+// ------------------------------------------------------------ zinv + curl
+// One line (kx, jy) per G threads.  NGRP = 1 (u) or 2 (u, b): each group of
+// 3 state components yields 6 fields: v and i k x v.
+template <typename T, int N, int NGRP>
+__global__ __launch_bounds__(LINE_BLOCK) void k_zinv(const cx<T>* __restrict__ st, cx<T>* __restrict__ A,
+                                                      const cx<T>* __restrict__ tw, Geo geo) {
+    using C = NCfg<N>;
+    using F = Fft<T, typename C::P, C::G, true>;
+    constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N);
+    __shared__ cx<T> sm[LPB * LS];
+    const int l = threadIdx.x / G, g = threadIdx.x % G;
+    const int64_t line = (int64_t)blockIdx.x * LPB + l;
+    const bool active = line < (int64_t)geo.nxk * geo.M;
+    const int kx = active ? (int)(line / geo.M) : 0;
+    const int jy = active ? (int)(line % geo.M) : 0;
+    const T fkx = T(kx), fky = T(k_of_j(jy, geo));
+    const LineLds<T> lds{sm + l * LS};
+    const int64_t lin = (int64_t)kx * geo.M + jy;
+    for (int grp = 0; grp < NGRP; ++grp) {
+        cx<T> u[3][E], w[3][E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = F::first_pos(g, e);
+            const int j = j_of_pos(p, geo);
+            const T fkz = T(k_of_pos(p, N));
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                u[c][e] = (active && j >= 0) ? st[(grp * 3 + c) * geo.sc + lin * geo.M + j] : czero<T>();
+            // w = i k x u
+            w[0][e] = mul_i(cx<T>{fky * u[2][e].x - fkz * u[1][e].x, fky * u[2][e].y - fkz * u[1][e].y});
+            w[1][e] = mul_i(cx<T>{fkz * u[0][e].x - fkx * u[2][e].x, fkz * u[0][e].y - fkx * u[2][e].y});
+            w[2][e] = mul_i(cx<T>{fkx * u[1][e].x - fky * u[0][e].x, fkx * u[1][e].y - fky * u[0][e].y});
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            F::run(u[c], g, lds, tw);
+            if (active) {
+                cx<T>* dst = A + (int64_t)(grp * 6 + c) * geo.sa + lin * N;
+#pragma unroll
+                for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = u[c][e];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            F::run(w[c], g, lds, tw);
+            if (active) {
+                cx<T>* dst = A + (int64_t)(grp * 6 + 3 + c) * geo.sa + lin * N;
+#pragma unroll
+                for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = w[c][e];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ y passes
+// Tile of TL consecutive z for one (field, kx).  INV: rows = kept ky (M) ->
+// all y (N); forward: all y -> kept ky.
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__(NCfg<N>::G * tile_lines<T>()) void k_ypass(const cx<T>* __restrict__ in,
+                                                                        cx<T>* __restrict__ out,
+                                                                        const cx<T>* __restrict__ tw, Geo geo,
+                                                                        int64_t fs_in, int64_t fs_out) {
+    using C = NCfg<N>;
+    using F = Fft<T, typename C::P, C::G, INV>;
+    constexpr int G = C::G, E = F::E, TL = tile_lines<T>(), TLP = TL + 1;
+    __shared__ cx<T> sm[N * TLP];
+    const int t = threadIdx.x % TL, g = threadIdx.x / TL;
+    const int z = blockIdx.x * TL + t;
+    const bool zin = z < N;
+    const int kx = blockIdx.y, f = blockIdx.z;
+    const int rows_in = INV ? geo.M : N, rows_out = INV ? N : geo.M;
+    const cx<T>* src = in + f * fs_in + (int64_t)kx * rows_in * N + z;
+    cx<T>* dst = out + f * fs_out + (int64_t)kx * rows_out * N + z;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = F::first_pos(g, e);
+        const int row = INV ? j_of_pos(p, geo) : p;
+        v[e] = (zin && row >= 0) ? src[(int64_t)row * N] : czero<T>();
+    }
+    F::run(v, g, TileLds<T, TLP>{sm + t}, tw);
+    if (zin) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int q = F::last_pos(g, e);
+            const int row = INV ? q : j_of_pos(q, geo);
+            if (row >= 0) dst[(int64_t)row * N] = v[e];
+        }
+    }
+}
+
+// ------------------------------------------------------------ fused x pass
+// Tile of TL consecutive z at one y.  Backward x for the field pairs
+// (v, i k x v) packed as one complex line each (two real transforms for the
+// price of one), cross products in registers, forward x of the products
+// packed two per complex line, split by Hermitian symmetry, kx <= K kept.
+template <typename T, int N, bool MHD>
+__global__ __launch_bounds__((NCfg<N>::G * xpass_lines<T, MHD, N>())) void k_xpass(const cx<T>* __restrict__ Bf,
+                                                                        cx<T>* __restrict__ Cf,
+                                                                        const cx<T>* __restrict__ tw, Geo geo) {
+    using C = NCfg<N>;
+    using FI = Fft<T, typename C::P, C::G, true, false>;
+    using FF = Fft<T, typename C::P, C::G, false, true>;
+    constexpr int G = C::G, E = FI::E, TL = xpass_lines<T, MHD, N>(), TLP = TL + 1;
+    constexpr int NP = MHD ? 6 : 3;   // backward pairs
+    constexpr int NO = MHD ? 3 : 2;   // forward packed lines
+    constexpr int NOUT = MHD ? 6 : 3; // output fields
+    __shared__ cx<T> sm[N * TLP];
+    const TileLds<T, TLP> lds{sm + threadIdx.x % TL};
+    const int t = threadIdx.x % TL, g = threadIdx.x / TL;
+    const int z = blockIdx.x * TL + t;
+    const bool zin = z < N;
+    const int y = blockIdx.y;
+    const int64_t nn = (int64_t)N * N;
+    const int64_t off = (int64_t)y * N + z;
+    const int K = geo.K;
+    cx<T> v[NP][E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = FI::first_pos(g, e);
+        const bool lo = p <= K, hi = p >= N - K;
+        const int kk = lo ? p : N - p;
+#pragma unroll
+        for (int pi = 0; pi < NP; ++pi) {
+            const int fu = (pi / 3) * 6 + pi % 3, fw = fu + 3;
+            cx<T> Z = czero<T>();
+            if (zin && (lo || hi)) {
+                const cx<T> U = Bf[fu * geo.sb + kk * nn + off];
+                const cx<T> W = Bf[fw * geo.sb + kk * nn + off];
+                if (p == 0) Z = {U.x, W.x};
+                else if (lo) Z = {U.x - W.y, U.y + W.x};
+                else Z = {U.x + W.y, W.x - U.y};
+            }
+            v[pi][e] = Z;
+        }
+    }
+#pragma unroll
+    for (int pi = 0; pi < NP; ++pi) FI::run(v[pi], g, lds, tw);
+    // physical space: Re = v, Im = curl v at x = last_pos(g, e)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const T ux = v[0][e].x, uy = v[1][e].x, uz = v[2][e].x;
+        const T wx = v[0][e].y, wy = v[1][e].y, wz = v[2][e].y;
+        T nx = uy * wz - uz * wy, ny = uz * wx - ux * wz, nz = ux * wy - uy * wx;
+        if constexpr (MHD) {
+            const T bx = v[3][e].x, by = v[4][e].x, bz = v[5][e].x;
+            const T jx = v[3][e].y, jy = v[4][e].y, jz = v[5][e].y;
+            nx += jy * bz - jz * by;
+            ny += jz * bx - jx * bz;
+            nz += jx * by - jy * bx;
+            const T mx = uy * bz - uz * by, my = uz * bx - ux * bz, mz = ux * by - uy * bx;
+            v[0][e] = {nx, ny};
+            v[1][e] = {nz, mx};
+            v[2][e] = {my, mz};
+        } else {
+            v[0][e] = {nx, ny};
+            v[1][e] = {nz, T(0)};
+        }
+    }
+#pragma unroll
+    for (int po = 0; po < NO; ++po) {
+        FF::run(v[po], g, lds, tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds(FF::last_pos(g, e)) = v[po][e];
+        __syncthreads();
+        if (zin) {
+            const int fa = 2 * po, fb = 2 * po + 1;
+            for (int kx = g; kx <= K; kx += G) {
+                const cx<T> a = lds(kx), b = lds(kx == 0 ? 0 : N - kx);
+                const cx<T> A = {T(0.5) * (a.x + b.x), T(0.5) * (a.y - b.y)};
+                Cf[fa * geo.sb + kx * nn + off] = A;
+                if (fb < NOUT) {
+                    const cx<T> Bv = {T(0.5) * (a.y + b.y), T(-0.5) * (a.x - b.x)};
+                    Cf[fb * geo.sb + kx * nn + off] = Bv;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ zfwd + update
+template <typename T>
+__device__ __forceinline__ void rk_apply(int mode, const RkArgs<T>& a, int grp, int64_t idx, int k2, cx<T> nk) {
+    if (mode == Z_RHS) {
+        a.R[idx] = nk;
+        return;
+    }
+    const T E = a.E[grp][k2], E2 = a.E2[grp][k2], h = a.h;
+    switch (mode) {
+        case Z_RK4_0: {
+            const cx<T> un = a.U[idx];
+            a.V[idx] = {E * (un.x + T(0.5) * h * nk.x), E * (un.y + T(0.5) * h * nk.y)};
+            a.Acc[idx] = {E2 * (un.x + (h / T(6)) * nk.x), E2 * (un.y + (h / T(6)) * nk.y)};
+        } break;
+        case Z_RK4_1: {
+            const cx<T> un = a.U[idx], ac = a.Acc[idx];
+            a.V[idx] = {E * un.x + T(0.5) * h * nk.x, E * un.y + T(0.5) * h * nk.y};
+            a.Acc[idx] = {ac.x + (h / T(3)) * E * nk.x, ac.y + (h / T(3)) * E * nk.y};
+        } break;
+        case Z_RK4_2: {
+            const cx<T> un = a.U[idx], ac = a.Acc[idx];
+            a.V[idx] = {E2 * un.x + h * E * nk.x, E2 * un.y + h * E * nk.y};
+            a.Acc[idx] = {ac.x + (h / T(3)) * E * nk.x, ac.y + (h / T(3)) * E * nk.y};
+        } break;
+        case Z_RK4_3: {
+            const cx<T> ac = a.Acc[idx];
+            a.U[idx] = {ac.x + (h / T(6)) * nk.x, ac.y + (h / T(6)) * nk.y};
+        } break;
+        case Z_RK2_0: {
+            const cx<T> un = a.U[idx];
+            a.V[idx] = {E2 * (un.x + h * nk.x), E2 * (un.y + h * nk.y)};
+            a.Acc[idx] = {E2 * (un.x + T(0.5) * h * nk.x), E2 * (un.y + T(0.5) * h * nk.y)};
+        } break;
+        case Z_RK2_1: {
+            const cx<T> ac = a.Acc[idx];
+            a.U[idx] = {ac.x + T(0.5) * h * nk.x, ac.y + T(0.5) * h * nk.y};
+        } break;
+        default: break;
+    }
+}
+
+template <typename T, int N, bool MHD>
+__global__ __launch_bounds__(LINE_BLOCK) void k_zfwd(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw,
+                                                      Geo geo, RkArgs<T> ra, int mode) {
+    using C = NCfg<N>;
+    using F = Fft<T, typename C::P, C::G, false>;
+    constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N);
+    constexpr int NF = MHD ? 6 : 3;
+    __shared__ cx<T> sm[LPB * LS];
+    const int l = threadIdx.x / G, g = threadIdx.x % G;
+    const int64_t line = (int64_t)blockIdx.x * LPB + l;
+    const bool active = line < (int64_t)geo.nxk * geo.M;
+    const int kx = active ? (int)(line / geo.M) : 0;
+    const int jy = active ? (int)(line % geo.M) : 0;
+    const int iky = k_of_j(jy, geo);
+    const LineLds<T> lds{sm + l * LS};
+    const int64_t lin = (int64_t)kx * geo.M + jy;
+    cx<T> v[NF][E];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const cx<T>* src = D + f * geo.sa + lin * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[f][e] = active ? src[F::first_pos(g, e)] : czero<T>();
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) F::run(v[f], g, lds, tw);
+    if (!active) return;
+    const T scale = T(1) / (T(N) * T(N) * T(N));
+    const T fkx = T(kx), fky = T(iky);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int q = F::last_pos(g, e);
+        const int j = j_of_pos(q, geo);
+        if (j < 0) continue;
+        const int ikz = k_of_pos(q, N);
+        const T fkz = T(ikz);
+        const int k2 = kx * kx + iky * iky + ikz * ikz;
+        const int64_t idx = lin * geo.M + j;
+        cx<T> n0 = cscale(v[0][e], scale), n1 = cscale(v[1][e], scale), n2 = cscale(v[2][e], scale);
+        // projection onto divergence-free fields: n - k (k . n) / |k|^2, zero at k = 0
+        cx<T> o[3];
+        if (k2 == 0) {
+            o[0] = o[1] = o[2] = czero<T>();
+        } else {
+            const T ik2 = T(1) / T(k2);
+            const cx<T> kn = {(fkx * n0.x + fky * n1.x + fkz * n2.x) * ik2, (fkx * n0.y + fky * n1.y + fkz * n2.y) * ik2};
+            o[0] = {n0.x - fkx * kn.x, n0.y - fkx * kn.y};
+            o[1] = {n1.x - fky * kn.x, n1.y - fky * kn.y};
+            o[2] = {n2.x - fkz * kn.x, n2.y - fkz * kn.y};
+        }
+        if (!MHD && ra.F && kx <= ra.kf && iky <= ra.kf && -iky <= ra.kf && ikz <= ra.kf && -ikz <= ra.kf) {
+            const int w = 2 * ra.kf + 1;
+            const int64_t fi = ((int64_t)kx * w + (iky + ra.kf)) * w + (ikz + ra.kf);
+            const int64_t fs = (int64_t)(ra.kf + 1) * w * w;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o[c] = cadd(o[c], ra.F[c * fs + fi]);
+        }
+        if (ra.lin_only) o[0] = o[1] = o[2] = czero<T>();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rk_apply(mode, ra, 0, c * geo.sc + idx, k2, o[c]);
+        if constexpr (MHD) {
+            // b: i k x F[u x b]
+            const cx<T> m0 = cscale(v[3][e], scale), m1 = cscale(v[4][e], scale), m2 = cscale(v[5][e], scale);
+            cx<T> b[3];
+            b[0] = mul_i(cx<T>{fky * m2.x - fkz * m1.x, fky * m2.y - fkz * m1.y});
+            b[1] = mul_i(cx<T>{fkz * m0.x - fkx * m2.x, fkz * m0.y - fkx * m2.y});
+            b[2] = mul_i(cx<T>{fkx * m1.x - fky * m0.x, fkx * m1.y - fky * m0.y});
+            if (ra.lin_only) b[0] = b[1] = b[2] = czero<T>();
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rk_apply(mode, ra, 1, (3 + c) * geo.sc + idx, k2, b[c]);
+        }
+    }
+}
+
+// ------------------------------------------------------------ standalone FFTs
+// Physical [nf][n][n][n] real, spectral [nf][n][n][n/2+1] complex (ABI layout).
+
+// x, forward: two real lines packed into one complex line, split afterwards.
+template <typename T, int N>
+__global__ __launch_bounds__(LINE_BLOCK) void k_fftx_r2c(const T* __restrict__ in, cx<T>* __restrict__ out,
+                                                          const cx<T>* __restrict__ tw, int64_t npairs) {
+    using C = NCfg<N>;
+    using F = Fft<T, typename C::P, C::G, false>;
+    constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N), NXH = N / 2 + 1;
+    __shared__ cx<T> sm[LPB * LS];
+    const int l = threadIdx.x / G, g = threadIdx.x % G;
+    const int64_t pair = (int64_t)blockIdx.x * LPB + l;
+    const bool active = pair < npairs;
+    const LineLds<T> lds{sm + l * LS};
+    const T* a = in + 2 * pair * N;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = F::first_pos(g, e);
+        v[e] = active ? cx<T>{a[p], a[N + p]} : czero<T>();
+    }
+    F::run(v, g, lds, tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds(F::last_pos(g, e)) = v[e];
+    __syncthreads();
+    if (!active) return;
+    cx<T>* oa = out + 2 * pair * NXH;
+    for (int k = g; k < NXH; k += G) {
+        const cx<T> z1 = lds(k), z2 = lds(k == 0 ? 0 : N - k);
+        oa[k] = {T(0.5) * (z1.x + z2.x), T(0.5) * (z1.y - z2.y)};
+        oa[NXH + k] = {T(0.5) * (z1.y + z2.y), T(-0.5) * (z1.x - z2.x)};
+    }
+}
+
+// x, backward: Hermitian extension of two half lines packed as A + i B.
+template <typename T, int N>
+__global__ __launch_bounds__(LINE_BLOCK) void k_fftx_c2r(const cx<T>* __restrict__ in, T* __restrict__ out,
+                                                          const cx<T>* __restrict__ tw, int64_t npairs) {
+    using C = NCfg<N>;
+    using F = Fft<T, typename C::P, C::G, true>;
+    constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N), NXH = N / 2 + 1;
+    __shared__ cx<T> sm[LPB * LS];
+    const int l = threadIdx.x / G, g = threadIdx.x % G;
+    const int64_t pair = (int64_t)blockIdx.x * LPB + l;
+    const bool active = pair < npairs;
+    const LineLds<T> lds{sm + l * LS};
+    const cx<T>* ia = in + 2 * pair * NXH;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = F::first_pos(g, e);
+        cx<T> Z = czero<T>();
+        if (active) {
+            if (p == 0 || 2 * p == N) {
+                Z = {ia[p].x, ia[NXH + p].x};
+            } else if (p < NXH) {
+                const cx<T> A = ia[p], B = ia[NXH + p];
+                Z = {A.x - B.y, A.y + B.x};
+            } else {
+                const cx<T> A = ia[N - p], B = ia[NXH + N - p];
+                Z = {A.x + B.y, B.x - A.y};
+            }
+        }
+        v[e] = Z;
+    }
+    F::run(v, g, lds, tw);
+    if (!active) return;
+    T* oa = out + 2 * pair * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int q = F::last_pos(g, e);
+        oa[q] = v[e].x;
+        oa[N + q] = v[e].y;
+    }
+}
+
+// Strided complex pass over rows of stride `rs` (elements), TL consecutive
+// columns per workgroup (ragged at ncols), planes of `ps` elements along
+// blockIdx.y.  Used for y (rs = n/2+1) and z (rs = n (n/2+1)) of the
+// standalone transforms; in == out is allowed.
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__(NCfg<N>::G * tile_lines<T>()) void k_fft_strided(const cx<T>* in, cx<T>* out,
+                                                                              const cx<T>* __restrict__ tw,
+                                                                              int64_t rs, int64_t ncols, int64_t ps,
+                                                                              T scale) {
+    using C = NCfg<N>;
+    using F = Fft<T, typename C::P, C::G, INV>;
+    constexpr int G = C::G, E = F::E, TL = tile_lines<T>(), TLP = TL + 1;
+    __shared__ cx<T> sm[N * TLP];
+    const int t = threadIdx.x % TL, g = threadIdx.x / TL;
+    const int64_t col = (int64_t)blockIdx.x * TL + t;
+    const bool cin = col < ncols;
+    const int64_t base = (int64_t)blockIdx.y * ps + col;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cin ? in[base + F::first_pos(g, e) * rs] : czero<T>();
+    F::run(v, g, TileLds<T, TLP>{sm + t}, tw);
+    if (cin) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) out[base + F::last_pos(g, e) * rs] = cscale(v[e], scale);
+    }
+}
+
+// ------------------------------------------------------------ launchers
+inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <typename T, int N>
+struct Impl {
+    using C = NCfg<N>;
+    static constexpr int TL = tile_lines<T>();
+    static constexpr int TB = C::G * TL;
+
+    static void zinv(pst_plan* P, const void* st) {
+        KTimer tm(P, PST_K_ZINV);
+        const Geo& g = P->geo;
+        unsigned nb = cdiv((int64_t)g.nxk * g.M, LINE_BLOCK / C::G);
+        if (P->ncomp == 6)
+            hipLaunchKernelGGL((k_zinv<T, N, 2>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
+                               (cx<T>*)P->A, (const cx<T>*)P->tw, g);
+        else
+            hipLaunchKernelGGL((k_zinv<T, N, 1>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
+                               (cx<T>*)P->A, (const cx<T>*)P->tw, g);
+    }
+    static void yinv(pst_plan* P) {
+        KTimer tm(P, PST_K_YINV);
+        const Geo& g = P->geo;
+        hipLaunchKernelGGL((k_ypass<T, N, true>), dim3(cdiv(N, TL), g.nxk, P->nfin), dim3(TB), 0, P->stream,
+                           (const cx<T>*)P->A, (cx<T>*)P->B, (const cx<T>*)P->tw, g, g.sa, g.sb);
+    }
+    static void xpass(pst_plan* P) {
+        KTimer tm(P, PST_K_XPASS);
+        const Geo& g = P->geo;
+        constexpr int TLM = xpass_lines<T, true, N>(), TLN = xpass_lines<T, false, N>();
+        if (P->ncomp == 6)
+            hipLaunchKernelGGL((k_xpass<T, N, true>), dim3(cdiv(N, TLM), N), dim3(C::G * TLM), 0, P->stream,
+                               (const cx<T>*)P->B, (cx<T>*)P->C, (const cx<T>*)P->tw, g);
+        else
+            hipLaunchKernelGGL((k_xpass<T, N, false>), dim3(cdiv(N, TLN), N), dim3(C::G * TLN), 0, P->stream,
+                               (const cx<T>*)P->B, (cx<T>*)P->C, (const cx<T>*)P->tw, g);
+    }
+    static void yfwd(pst_plan* P) {
+        KTimer tm(P, PST_K_YFWD);
+        const Geo& g = P->geo;
+        hipLaunchKernelGGL((k_ypass<T, N, false>), dim3(cdiv(N, TL), g.nxk, P->nfout), dim3(TB), 0, P->stream,
+                           (const cx<T>*)P->C, (cx<T>*)P->A, (const cx<T>*)P->tw, g, g.sb, g.sa);
+    }
+    static void zfwd(pst_plan* P, int mode, void* rhs_out) {
+        KTimer tm(P, PST_K_ZFWD);
+        const Geo& g = P->geo;
+        RkArgs<T> ra;
+        ra.U = (cx<T>*)P->U;
+        ra.V = (cx<T>*)P->V;
+        ra.Acc = (cx<T>*)P->Acc;
+        ra.R = (cx<T>*)rhs_out;
+        for (int i = 0; i < 2; ++i) {
+            ra.E[i] = (const T*)P->Etab[i];
+            ra.E2[i] = (const T*)P->E2tab[i];
+        }
+        ra.h = (T)P->p.dt;
+        ra.F = (const cx<T>*)P->force;
+        ra.kf = P->kf;
+        ra.lin_only = (P->p.flags & PST_FLAG_LINEAR_ONLY) ? 1 : 0;
+        unsigned nb = cdiv((int64_t)g.nxk * g.M, LINE_BLOCK / C::G);
+        if (P->ncomp == 6)
+            hipLaunchKernelGGL((k_zfwd<T, N, true>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+                               (const cx<T>*)P->tw, g, ra, mode);
+        else
+            hipLaunchKernelGGL((k_zfwd<T, N, false>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+                               (const cx<T>*)P->tw, g, ra, mode);
+    }
+    static void fft_r2c(pst_plan* P, const void* in, void* out, int nf) {
+        const int64_t nxh = N / 2 + 1, plane = (int64_t)N * nxh;
+        const int64_t npairs = (int64_t)nf * N * N / 2;
+        {
+            KTimer tm(P, PST_K_FFTX);
+            hipLaunchKernelGGL((k_fftx_r2c<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                               P->stream, (const T*)in, (cx<T>*)out, (const cx<T>*)P->tw, npairs);
+        }
+        {
+            KTimer tm(P, PST_K_FFTY);
+            hipLaunchKernelGGL((k_fft_strided<T, N, false>), dim3(cdiv(nxh, TL), (unsigned)(nf * N)), dim3(TB), 0,
+                               P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, nxh, nxh, plane, T(1));
+        }
+        {
+            KTimer tm(P, PST_K_FFTZ);
+            const T s = T(1) / (T(N) * T(N) * T(N));
+            hipLaunchKernelGGL((k_fft_strided<T, N, false>), dim3(cdiv(plane, TL), (unsigned)nf), dim3(TB), 0,
+                               P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, plane, plane,
+                               (int64_t)N * plane, s);
+        }
+    }
+    static void fft_c2r(pst_plan* P, const void* in, void* out, int nf, void* tmp) {
+        const int64_t nxh = N / 2 + 1, plane = (int64_t)N * nxh;
+        const int64_t npairs = (int64_t)nf * N * N / 2;
+        {
+            KTimer tm(P, PST_K_FFTZ);
+            hipLaunchKernelGGL((k_fft_strided<T, N, true>), dim3(cdiv(plane, TL), (unsigned)nf), dim3(TB), 0,
+                               P->stream, (const cx<T>*)in, (cx<T>*)tmp, (const cx<T>*)P->tw, plane, plane,
+                               (int64_t)N * plane, T(1));
+        }
+        {
+            KTimer tm(P, PST_K_FFTY);
+            hipLaunchKernelGGL((k_fft_strided<T, N, true>), dim3(cdiv(nxh, TL), (unsigned)(nf * N)), dim3(TB), 0,
+                               P->stream, (const cx<T>*)tmp, (cx<T>*)tmp, (const cx<T>*)P->tw, nxh, nxh, plane, T(1));
+        }
+        {
+            KTimer tm(P, PST_K_FFTX);
+            hipLaunchKernelGGL((k_fftx_c2r<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                               P->stream, (const cx<T>*)tmp, (T*)out, (const cx<T>*)P->tw, npairs);
+        }
+    }
+
+    static const Launchers* get() {
+        static Launchers L = [] {
+            Launchers l{};
+            l.n = N;
+            for (int i = 0; i < 4; ++i) l.radices[i] = i < C::P::S ? C::P::r[i] : 0;
+            l.tile_lines = TL;
+            l.zinv = &zinv;
+            l.yinv = &yinv;
+            l.xpass = &xpass;
+            l.yfwd = &yfwd;
+            l.zfwd = &zfwd;
+            l.fft_r2c = &fft_r2c;
+            l.fft_c2r = &fft_c2r;
+            return l;
+        }();
+        return &L;
+    }
+};
+
+}  // namespace pst
+
+#define PST_INSTANTIATE_N(NVAL)                                                          \
+    namespace pst {                                                                      \
+    const Launchers* launchers_n##NVAL(int precision) {                                  \
+        return precision == PST_FP64 ? Impl<double, NVAL>::get() : Impl<float, NVAL>::get(); \
+    }                                                                                    \
+    }

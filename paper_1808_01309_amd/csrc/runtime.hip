@@ -1,0 +1,740 @@
+// Host runtime of the C ABI (include/pst.h): plan life cycle, state I/O,
+// time stepping, diagnostics, standalone transforms and timers, plus the
+// size-independent kernels (gather / scatter between the ABI spectral layout
+// and the dealiased compact state, FP64 reductions).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "fft_engine.h"
+#include "plan.h"
+
+using namespace pst;
+
+// --------------------------------------------------------------- registry
+namespace pst {
+#define PST_DECL_N(NV) const Launchers* launchers_n##NV(int precision);
+PST_DECL_N(16) PST_DECL_N(24) PST_DECL_N(32) PST_DECL_N(48) PST_DECL_N(64) PST_DECL_N(96)
+PST_DECL_N(128) PST_DECL_N(256) PST_DECL_N(512) PST_DECL_N(1024)
+#undef PST_DECL_N
+
+const Launchers* launchers_for(int n, int precision) {
+    switch (n) {
+        case 16: return launchers_n16(precision);
+        case 24: return launchers_n24(precision);
+        case 32: return launchers_n32(precision);
+        case 48: return launchers_n48(precision);
+        case 64: return launchers_n64(precision);
+        case 96: return launchers_n96(precision);
+        case 128: return launchers_n128(precision);
+        case 256: return launchers_n256(precision);
+        case 512: return launchers_n512(precision);
+        case 1024: return launchers_n1024(precision);
+        default: return nullptr;
+    }
+}
+}  // namespace pst
+
+// --------------------------------------------------------------- errors
+static thread_local std::string g_create_err;
+
+static pst_status fail(pst_plan* P, pst_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (P) P->err = buf;
+    else g_create_err = buf;
+    return s;
+}
+
+#define HIPCHK(P, call)                                                                           \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail((P), PST_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));         \
+    } while (0)
+
+static pst_status check_launch(pst_plan* P, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(P, PST_ERR_HIP, "%s: kernel launch failed: %s", what, hipGetErrorString(e));
+    return PST_OK;
+}
+
+extern "C" const char* pst_status_str(pst_status s) {
+    switch (s) {
+        case PST_OK: return "ok";
+        case PST_ERR_INVALID_ARG: return "invalid argument";
+        case PST_ERR_UNSUPPORTED_N: return "unsupported grid size";
+        case PST_ERR_OOM: return "out of device memory";
+        case PST_ERR_HIP: return "HIP runtime error";
+        case PST_ERR_NONFINITE: return "non-finite value";
+        case PST_ERR_UNSUPPORTED: return "unsupported option";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* pst_last_error(const pst_plan* P) { return P ? P->err.c_str() : g_create_err.c_str(); }
+
+extern "C" int pst_supported_n(int n) {
+    switch (n) {
+        case 16: case 24: case 32: case 48: case 64: case 96: case 128: case 256: case 512: case 1024: return 1;
+        default: return 0;
+    }
+}
+
+// --------------------------------------------------------------- timers
+namespace pst {
+KTimer::KTimer(pst_plan* plan, int k) : P(plan), kind(k) {
+    if (!(P->p.flags & PST_FLAG_TIMERS)) return;
+    for (hipEvent_t* ev : {&a, &b}) {
+        if (!P->pool.empty()) {
+            *ev = P->pool.back();
+            P->pool.pop_back();
+        } else if (hipEventCreate(ev) != hipSuccess) {
+            *ev = nullptr;
+        }
+    }
+    if (a) hipEventRecord(a, P->stream);
+}
+KTimer::~KTimer() {
+    if (!(P->p.flags & PST_FLAG_TIMERS) || !a || !b) return;
+    hipEventRecord(b, P->stream);
+    P->pending.push_back({kind, a, b});
+}
+}  // namespace pst
+
+static void drain_timers(pst_plan* P) {
+    for (auto& r : P->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            P->t_ms[r.kind] += ms;
+            P->t_cnt[r.kind] += 1;
+        }
+        P->pool.push_back(r.a);
+        P->pool.push_back(r.b);
+    }
+    P->pending.clear();
+}
+
+// --------------------------------------------------------------- small kernels
+template <typename T>
+__global__ void k_gather(const cx<T>* __restrict__ abi, cx<T>* __restrict__ st, Geo g, int ncomp) {
+    const int64_t total = (int64_t)ncomp * g.sc;
+    const int nxh = g.n / 2 + 1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i / g.sc);
+        int64_t r = i % g.sc;
+        const int jz = (int)(r % g.M);
+        r /= g.M;
+        const int jy = (int)(r % g.M);
+        const int kx = (int)(r / g.M);
+        const int ky = k_of_j(jy, g), kz = k_of_j(jz, g);
+        const int iy = (ky + g.n) % g.n, iz = (kz + g.n) % g.n;
+        const cx<T>* a = abi + (int64_t)c * g.n * g.n * nxh;
+        cx<T> v = a[((int64_t)iz * g.n + iy) * nxh + kx];
+        if (kx == 0) {
+            const cx<T> m = a[((int64_t)((g.n - iz) % g.n) * g.n + (g.n - iy) % g.n) * nxh];
+            v = {T(0.5) * (v.x + m.x), T(0.5) * (v.y - m.y)};
+        }
+        st[i] = v;
+    }
+}
+
+template <typename T>
+__global__ void k_scatter(const cx<T>* __restrict__ st, cx<T>* __restrict__ abi, Geo g, int ncomp) {
+    const int nxh = g.n / 2 + 1;
+    const int64_t per = (int64_t)g.n * g.n * nxh, total = (int64_t)ncomp * per;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i / per);
+        int64_t r = i % per;
+        const int kx = (int)(r % nxh);
+        r /= nxh;
+        const int iy = (int)(r % g.n), iz = (int)(r / g.n);
+        const int ky = k_of_pos(iy, g.n), kz = k_of_pos(iz, g.n);
+        cx<T> v = {T(0), T(0)};
+        if (kx <= g.K && ky <= g.K && -ky <= g.K && kz <= g.K && -kz <= g.K) {
+            const int jy = ky >= 0 ? ky : ky + g.M, jz = kz >= 0 ? kz : kz + g.M;
+            v = st[(int64_t)c * g.sc + ((int64_t)kx * g.M + jy) * g.M + jz];
+        }
+        abi[i] = v;
+    }
+}
+
+// Energy partials: block b sums w |v|^2 over its grid-stride share of the
+// modes of components [c0, c0 + 3) in a fixed order -> partial[b] (double).
+constexpr int RED_BLOCKS = 1024, RED_THREADS = 256;
+
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_energy_part(const cx<T>* __restrict__ st, Geo g, int c0,
+                                                             double* __restrict__ part) {
+    __shared__ double sh[RED_THREADS];
+    double acc = 0.0;
+    const int64_t per = g.sc;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (int64_t)gridDim.x * blockDim.x) {
+        const int kx = (int)(i / ((int64_t)g.M * g.M));
+        const double w = kx == 0 ? 1.0 : 2.0;
+        double s = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const cx<T> v = st[(int64_t)(c0 + c) * per + i];
+            s += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
+        acc += w * s;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_sum_final(const double* __restrict__ part, int np, double* out,
+                                                           double scale) {
+    __shared__ double sh[RED_THREADS];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < np; i += RED_THREADS) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = scale * sh[0];
+}
+
+constexpr int MAX_SHELLS = 2048;
+
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_spectrum(const cx<T>* __restrict__ st, Geo g, int c0,
+                                                          double* __restrict__ bins, int nshells) {
+    __shared__ double sh[MAX_SHELLS];
+    for (int i = threadIdx.x; i < nshells; i += RED_THREADS) sh[i] = 0.0;
+    __syncthreads();
+    const int64_t per = g.sc;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (int64_t)gridDim.x * blockDim.x) {
+        const int jz = (int)(i % g.M);
+        const int jy = (int)((i / g.M) % g.M);
+        const int kx = (int)(i / ((int64_t)g.M * g.M));
+        const int ky = k_of_j(jy, g), kz = k_of_j(jz, g);
+        const long k2 = (long)kx * kx + (long)ky * ky + (long)kz * kz;
+        const int s = (int)floor(sqrt((double)k2) + 0.5);
+        if (s >= nshells) continue;
+        double a = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const cx<T> v = st[(int64_t)(c0 + c) * per + i];
+            a += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
+        atomicAdd(&sh[s], 0.5 * (kx == 0 ? 1.0 : 2.0) * a);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nshells; i += RED_THREADS)
+        if (sh[i] != 0.0) atomicAdd(&bins[i], sh[i]);
+}
+
+// --------------------------------------------------------------- helpers
+static unsigned grid_for(int64_t total, int threads = 256) {
+    int64_t b = (total + threads - 1) / threads;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+static pst_status dalloc(pst_plan* P, void** ptr, size_t bytes) {
+    *ptr = nullptr;
+    if (bytes == 0) return PST_OK;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(P, PST_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    P->owned_bytes += bytes;
+    return PST_OK;
+}
+
+static size_t abi_spec_bytes(const pst_plan* P, int ncomp) {
+    const size_t n = (size_t)P->p.n;
+    return (size_t)ncomp * n * n * (n / 2 + 1) * P->esz;
+}
+
+static pst_status ensure_abi(pst_plan* P, size_t bytes) {
+    if (P->abi_bytes >= bytes) return PST_OK;
+    if (P->abi) {
+        hipStreamSynchronize(P->stream);
+        hipFree(P->abi);
+        P->owned_bytes -= P->abi_bytes;
+        P->abi = nullptr;
+        P->abi_bytes = 0;
+    }
+    pst_status s = dalloc(P, &P->abi, bytes);
+    if (s == PST_OK) P->abi_bytes = bytes;
+    return s;
+}
+
+// host tables in FP64, rounded once to the plan precision
+template <typename T>
+static pst_status upload_tables(pst_plan* P) {
+    const int n = P->p.n, K = P->geo.K;
+    std::vector<cx<T>> tw(n);
+    for (int m = 0; m < n; ++m) {
+        // exp(-2 pi i m / n) evaluated in extended precision, rounded once
+        const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
+        tw[m].x = (T)cosl(a);
+        tw[m].y = (T)(-sinl(a));
+    }
+    HIPCHK(P, hipMemcpy(P->tw, tw.data(), sizeof(cx<T>) * n, hipMemcpyHostToDevice));
+    const int nk2 = 3 * K * K + 1;
+    for (int grp = 0; grp < 2; ++grp) {
+        const double visc = grp == 0 ? P->p.nu : P->p.eta;
+        std::vector<T> E(nk2), E2(nk2);
+        for (int k2 = 0; k2 < nk2; ++k2) {
+            const double e = exp(-visc * (double)k2 * P->p.dt * 0.5);
+            E[k2] = (T)e;
+            E2[k2] = (T)(e * e);
+        }
+        HIPCHK(P, hipMemcpy(P->Etab[grp], E.data(), sizeof(T) * nk2, hipMemcpyHostToDevice));
+        HIPCHK(P, hipMemcpy(P->E2tab[grp], E2.data(), sizeof(T) * nk2, hipMemcpyHostToDevice));
+    }
+    return PST_OK;
+}
+
+// --------------------------------------------------------------- plan
+extern "C" void pst_plan_destroy(pst_plan* P) {
+    if (!P) return;
+    hipStreamSynchronize(P->stream);
+    void* bufs[] = {P->U, P->V, P->Acc, P->A, P->B, P->C, P->tw, P->Etab[0], P->Etab[1],
+                    P->E2tab[0], P->E2tab[1], P->force, P->abi, P->red};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    for (auto& r : P->pending) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (auto e : P->pool) hipEventDestroy(e);
+    delete P;
+}
+
+extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst_plan** out) {
+    g_create_err.clear();
+    if (!out) return fail(nullptr, PST_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(nullptr, PST_ERR_INVALID_ARG, "params is NULL");
+    if (p->solver != PST_NS && p->solver != PST_MHD) return fail(nullptr, PST_ERR_INVALID_ARG, "solver %d", p->solver);
+    if (p->precision != PST_FP32 && p->precision != PST_FP64)
+        return fail(nullptr, PST_ERR_INVALID_ARG, "precision %d", p->precision);
+    if (p->rk_order != 2 && p->rk_order != 4) return fail(nullptr, PST_ERR_INVALID_ARG, "rk_order %d", p->rk_order);
+    if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(nullptr, PST_ERR_INVALID_ARG, "dt must be > 0");
+    if (!(p->nu >= 0.0) || !isfinite(p->nu)) return fail(nullptr, PST_ERR_INVALID_ARG, "nu must be >= 0");
+    if (p->solver == PST_MHD && (!(p->eta >= 0.0) || !isfinite(p->eta)))
+        return fail(nullptr, PST_ERR_INVALID_ARG, "eta must be >= 0");
+    if (p->dealias != PST_DEALIAS_CUBE) return fail(nullptr, PST_ERR_UNSUPPORTED, "dealias %d", p->dealias);
+    if (p->flags & ~(unsigned)(PST_FLAG_LINEAR_ONLY | PST_FLAG_TIMERS))
+        return fail(nullptr, PST_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
+    if (!pst_supported_n(p->n)) return fail(nullptr, PST_ERR_UNSUPPORTED_N, "n = %d not supported", p->n);
+    const Launchers* L = launchers_for(p->n, p->precision);
+    if (!L) return fail(nullptr, PST_ERR_UNSUPPORTED_N, "n = %d has no kernels", p->n);
+
+    pst_plan* P = new pst_plan();
+    P->p = *p;
+    if (P->p.solver == PST_NS) P->p.eta = P->p.nu;
+    P->stream = (hipStream_t)hip_stream;
+    P->L = L;
+    P->esz = p->precision == PST_FP64 ? 16 : 8;
+    const int n = p->n, K = (n + 2) / 3 - 1, M = 2 * K + 1;
+    P->geo.n = n;
+    P->geo.K = K;
+    P->geo.M = M;
+    P->geo.nxk = K + 1;
+    P->geo.sc = (int64_t)(K + 1) * M * M;
+    P->geo.sa = (int64_t)(K + 1) * M * n;
+    P->geo.sb = (int64_t)(K + 1) * n * n;
+    const bool mhd = p->solver == PST_MHD;
+    P->ncomp = mhd ? 6 : 3;
+    P->nfin = mhd ? 12 : 6;
+    P->nfout = mhd ? 6 : 3;
+    P->kf = -1;
+    const size_t es = P->esz, tsz = p->precision == PST_FP64 ? 8 : 4;
+    pst_status s = PST_OK;
+#define ALLOC(ptr, bytes)                                   \
+    do {                                                    \
+        s = dalloc(P, (void**)&(ptr), (bytes));             \
+        if (s != PST_OK) {                                  \
+            g_create_err = P->err;                          \
+            pst_plan_destroy(P);                            \
+            return s;                                       \
+        }                                                   \
+    } while (0)
+    const size_t st_bytes = (size_t)P->ncomp * P->geo.sc * es;
+    ALLOC(P->U, st_bytes);
+    ALLOC(P->V, st_bytes);
+    ALLOC(P->Acc, st_bytes);
+    ALLOC(P->A, (size_t)P->nfin * P->geo.sa * es);
+    ALLOC(P->B, (size_t)P->nfin * P->geo.sb * es);
+    ALLOC(P->C, (size_t)P->nfout * P->geo.sb * es);
+    ALLOC(P->tw, (size_t)n * es);
+    const size_t nk2 = 3 * (size_t)K * K + 1;
+    for (int i = 0; i < 2; ++i) {
+        ALLOC(P->Etab[i], nk2 * tsz);
+        ALLOC(P->E2tab[i], nk2 * tsz);
+    }
+    ALLOC(P->red, sizeof(double) * (RED_BLOCKS + MAX_SHELLS + 8));
+#undef ALLOC
+    hipError_t e = hipMemsetAsync(P->U, 0, st_bytes, P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) {
+        fail(nullptr, PST_ERR_HIP, "initialising state failed: %s", hipGetErrorString(e));
+        pst_plan_destroy(P);
+        return PST_ERR_HIP;
+    }
+    s = p->precision == PST_FP64 ? upload_tables<double>(P) : upload_tables<float>(P);
+    if (s != PST_OK) {
+        g_create_err = P->err;
+        pst_plan_destroy(P);
+        return s;
+    }
+    *out = P;
+    return PST_OK;
+}
+
+extern "C" pst_status pst_query(const pst_plan* P, pst_info* info) {
+    if (!P || !info) return PST_ERR_INVALID_ARG;
+    info->n = P->p.n;
+    info->kcut = P->geo.K;
+    info->ncomp = P->ncomp;
+    info->modes_per_comp = (size_t)P->geo.sc;
+    info->workspace_bytes = P->owned_bytes;
+    for (int i = 0; i < 4; ++i) info->radices[i] = P->L->radices[i];
+    info->tile_lines = P->L->tile_lines;
+    info->steps_done = P->steps;
+    return PST_OK;
+}
+
+// --------------------------------------------------------------- state I/O
+static bool valid_field(const pst_plan* P, int field) {
+    return field == PST_FIELD_U || (field == PST_FIELD_B && P->ncomp == 6);
+}
+
+template <typename T>
+static void launch_gather(pst_plan* P, const void* abi, void* st) {
+    KTimer tm(P, PST_K_OTHER);
+    hipLaunchKernelGGL((k_gather<T>), dim3(grid_for(3 * P->geo.sc)), dim3(256), 0, P->stream, (const cx<T>*)abi,
+                       (cx<T>*)st, P->geo, 3);
+}
+template <typename T>
+static void launch_scatter(pst_plan* P, const void* st, void* abi, int ncomp) {
+    KTimer tm(P, PST_K_OTHER);
+    const int64_t tot = (int64_t)ncomp * P->p.n * P->p.n * (P->p.n / 2 + 1);
+    hipLaunchKernelGGL((k_scatter<T>), dim3(grid_for(tot)), dim3(256), 0, P->stream, (const cx<T>*)st,
+                       (cx<T>*)abi, P->geo, ncomp);
+}
+
+static void gather(pst_plan* P, const void* abi, void* st) {
+    if (P->p.precision == PST_FP64) launch_gather<double>(P, abi, st);
+    else launch_gather<float>(P, abi, st);
+}
+static void scatter(pst_plan* P, const void* st, void* abi, int ncomp) {
+    if (P->p.precision == PST_FP64) launch_scatter<double>(P, st, abi, ncomp);
+    else launch_scatter<float>(P, st, abi, ncomp);
+}
+
+extern "C" pst_status pst_set_state(pst_plan* P, int field, int space, const void* src, int mem) {
+    if (!P) return PST_ERR_INVALID_ARG;
+    if (!src) return fail(P, PST_ERR_INVALID_ARG, "src is NULL");
+    if (!valid_field(P, field)) return fail(P, PST_ERR_INVALID_ARG, "field %d invalid for this solver", field);
+    if (space != PST_SPACE_PHYS && space != PST_SPACE_SPEC) return fail(P, PST_ERR_INVALID_ARG, "space %d", space);
+    if (mem != PST_MEM_HOST && mem != PST_MEM_DEVICE) return fail(P, PST_ERR_INVALID_ARG, "mem %d", mem);
+    const size_t n = P->p.n;
+    const size_t spec = abi_spec_bytes(P, 3);
+    const size_t phys = 3 * n * n * n * (P->esz / 2);
+    // layout of the scratch: [spectral (3 comps)] [physical staging if needed]
+    const size_t need = spec + ((space == PST_SPACE_PHYS && mem == PST_MEM_HOST) ? phys : 0);
+    pst_status s = ensure_abi(P, need);
+    if (s) return s;
+    char* spec_buf = (char*)P->abi;
+    if (space == PST_SPACE_SPEC) {
+        if (mem == PST_MEM_HOST) {
+            HIPCHK(P, hipMemcpyAsync(spec_buf, src, spec, hipMemcpyHostToDevice, P->stream));
+        } else {
+            HIPCHK(P, hipMemcpyAsync(spec_buf, src, spec, hipMemcpyDeviceToDevice, P->stream));
+        }
+    } else {
+        const void* phys_dev = src;
+        if (mem == PST_MEM_HOST) {
+            HIPCHK(P, hipMemcpyAsync(spec_buf + spec, src, phys, hipMemcpyHostToDevice, P->stream));
+            phys_dev = spec_buf + spec;
+        }
+        P->L->fft_r2c(P, phys_dev, spec_buf, 3);
+        if ((s = check_launch(P, "fft_r2c"))) return s;
+    }
+    char* st = (char*)P->U + (size_t)field * 3 * P->geo.sc * P->esz;
+    gather(P, spec_buf, st);
+    if ((s = check_launch(P, "gather"))) return s;
+    if (mem == PST_MEM_HOST) HIPCHK(P, hipStreamSynchronize(P->stream));
+    P->steps = 0;
+    return PST_OK;
+}
+
+extern "C" pst_status pst_get_state(pst_plan* P, int field, int space, void* dst, int mem) {
+    if (!P) return PST_ERR_INVALID_ARG;
+    if (!dst) return fail(P, PST_ERR_INVALID_ARG, "dst is NULL");
+    if (!valid_field(P, field)) return fail(P, PST_ERR_INVALID_ARG, "field %d invalid for this solver", field);
+    if (space != PST_SPACE_PHYS && space != PST_SPACE_SPEC) return fail(P, PST_ERR_INVALID_ARG, "space %d", space);
+    if (mem != PST_MEM_HOST && mem != PST_MEM_DEVICE) return fail(P, PST_ERR_INVALID_ARG, "mem %d", mem);
+    const size_t n = P->p.n;
+    const size_t spec = abi_spec_bytes(P, 3);
+    const size_t phys = 3 * n * n * n * (P->esz / 2);
+    // scratch: [spectral] [c2r workspace (spectral)] [physical staging]
+    const size_t need = space == PST_SPACE_SPEC ? spec : 2 * spec + (mem == PST_MEM_HOST ? phys : 0);
+    pst_status s = ensure_abi(P, need);
+    if (s) return s;
+    char* spec_buf = (char*)P->abi;
+    const char* st = (const char*)P->U + (size_t)field * 3 * P->geo.sc * P->esz;
+    if (space == PST_SPACE_SPEC) {
+        void* target = mem == PST_MEM_DEVICE ? dst : (void*)spec_buf;
+        scatter(P, st, target, 3);
+        if ((s = check_launch(P, "scatter"))) return s;
+        if (mem == PST_MEM_HOST) {
+            HIPCHK(P, hipMemcpyAsync(dst, spec_buf, spec, hipMemcpyDeviceToHost, P->stream));
+            HIPCHK(P, hipStreamSynchronize(P->stream));
+        }
+    } else {
+        scatter(P, st, spec_buf, 3);
+        void* target = mem == PST_MEM_DEVICE ? dst : (void*)(spec_buf + 2 * spec);
+        P->L->fft_c2r(P, spec_buf, target, 3, spec_buf + spec);
+        if ((s = check_launch(P, "fft_c2r"))) return s;
+        if (mem == PST_MEM_HOST) {
+            HIPCHK(P, hipMemcpyAsync(dst, target, phys, hipMemcpyDeviceToHost, P->stream));
+            HIPCHK(P, hipStreamSynchronize(P->stream));
+        }
+    }
+    return PST_OK;
+}
+
+// forcing: keep the box |k_i| <= kf that holds every nonzero mode
+template <typename T>
+static pst_status set_forcing_t(pst_plan* P, const cx<T>* h /*host ABI layout*/) {
+    const int n = P->p.n, nxh = n / 2 + 1, K = P->geo.K;
+    int kf = -1;
+    for (int c = 0; c < 3; ++c)
+        for (int z = 0; z < n; ++z)
+            for (int y = 0; y < n; ++y)
+                for (int x = 0; x < nxh; ++x) {
+                    const cx<T> v = h[(((size_t)c * n + z) * n + y) * nxh + x];
+                    if (v.x == T(0) && v.y == T(0)) continue;
+                    const int ky = k_of_pos(y, n), kz = k_of_pos(z, n);
+                    if (x > K || abs(ky) > K || abs(kz) > K) continue;  // dealiased away
+                    int m = x;
+                    if (abs(ky) > m) m = abs(ky);
+                    if (abs(kz) > m) m = abs(kz);
+                    if (m > kf) kf = m;
+                }
+    if (P->force) {
+        hipStreamSynchronize(P->stream);
+        hipFree(P->force);
+        P->force = nullptr;
+    }
+    P->kf = -1;
+    if (kf < 0) return PST_OK;
+    const int w = 2 * kf + 1;
+    const size_t fs = (size_t)(kf + 1) * w * w;
+    std::vector<cx<T>> box(3 * fs);
+    for (int c = 0; c < 3; ++c)
+        for (int kx = 0; kx <= kf; ++kx)
+            for (int ky = -kf; ky <= kf; ++ky)
+                for (int kz = -kf; kz <= kf; ++kz) {
+                    const int y = (ky + n) % n, z = (kz + n) % n;
+                    cx<T> v = h[(((size_t)c * n + z) * n + y) * nxh + kx];
+                    if (kx == 0) {  // Hermitian part, as for the state
+                        const cx<T> m = h[(((size_t)c * n + (n - z) % n) * n + (n - y) % n) * nxh];
+                        v = {T(0.5) * (v.x + m.x), T(0.5) * (v.y - m.y)};
+                    }
+                    box[c * fs + ((size_t)kx * w + (ky + kf)) * w + (kz + kf)] = v;
+                }
+    void* d = nullptr;
+    if (hipMalloc(&d, sizeof(cx<T>) * 3 * fs) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(P, PST_ERR_OOM, "forcing box allocation failed");
+    }
+    if (hipMemcpy(d, box.data(), sizeof(cx<T>) * 3 * fs, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(d);
+        return fail(P, PST_ERR_HIP, "forcing upload failed");
+    }
+    P->force = d;
+    P->kf = kf;
+    return PST_OK;
+}
+
+extern "C" pst_status pst_set_forcing(pst_plan* P, const void* fhat, int mem) {
+    if (!P) return PST_ERR_INVALID_ARG;
+    if (P->ncomp != 3) return fail(P, PST_ERR_INVALID_ARG, "forcing is defined for the Navier-Stokes solver only");
+    if (mem != PST_MEM_HOST && mem != PST_MEM_DEVICE) return fail(P, PST_ERR_INVALID_ARG, "mem %d", mem);
+    const size_t bytes = abi_spec_bytes(P, 3);
+    std::vector<char> host;
+    const void* h = fhat;
+    if (fhat && mem == PST_MEM_DEVICE) {
+        host.resize(bytes);
+        HIPCHK(P, hipStreamSynchronize(P->stream));
+        HIPCHK(P, hipMemcpy(host.data(), fhat, bytes, hipMemcpyDeviceToHost));
+        h = host.data();
+    }
+    if (!h) {
+        if (P->force) {
+            hipStreamSynchronize(P->stream);
+            hipFree(P->force);
+            P->force = nullptr;
+        }
+        P->kf = -1;
+        return PST_OK;
+    }
+    return P->p.precision == PST_FP64 ? set_forcing_t<double>(P, (const cx<double>*)h)
+                                      : set_forcing_t<float>(P, (const cx<float>*)h);
+}
+
+// --------------------------------------------------------------- rhs / step
+static pst_status run_rhs_passes(pst_plan* P, const void* state, int mode, void* rhs_out) {
+    pst_status s;
+    P->L->zinv(P, state);
+    if ((s = check_launch(P, "zinv"))) return s;
+    P->L->yinv(P);
+    if ((s = check_launch(P, "yinv"))) return s;
+    P->L->xpass(P);
+    if ((s = check_launch(P, "xpass"))) return s;
+    P->L->yfwd(P);
+    if ((s = check_launch(P, "yfwd"))) return s;
+    P->L->zfwd(P, mode, rhs_out);
+    return check_launch(P, "zfwd");
+}
+
+extern "C" pst_status pst_rhs(pst_plan* P, const void* state_dev, void* rhs_dev) {
+    if (!P) return PST_ERR_INVALID_ARG;
+    if (!state_dev || !rhs_dev) return fail(P, PST_ERR_INVALID_ARG, "NULL buffer");
+    const size_t spec = abi_spec_bytes(P, P->ncomp);
+    const size_t cbytes = (size_t)P->ncomp * P->geo.sc * P->esz;
+    pst_status s = ensure_abi(P, 2 * cbytes);
+    if (s) return s;
+    char* cst = (char*)P->abi;          // compact copy of the input state
+    char* crhs = cst + cbytes;          // compact rhs
+    (void)spec;
+    for (int grp = 0; grp < P->ncomp / 3; ++grp) {
+        const char* src = (const char*)state_dev + (size_t)grp * abi_spec_bytes(P, 3);
+        gather(P, src, cst + (size_t)grp * 3 * P->geo.sc * P->esz);
+    }
+    if ((s = check_launch(P, "gather"))) return s;
+    if ((s = run_rhs_passes(P, cst, Z_RHS, crhs))) return s;
+    scatter(P, crhs, rhs_dev, P->ncomp);
+    return check_launch(P, "scatter");
+}
+
+extern "C" pst_status pst_step(pst_plan* P, int nsteps) {
+    if (!P) return PST_ERR_INVALID_ARG;
+    if (nsteps < 0) return fail(P, PST_ERR_INVALID_ARG, "nsteps < 0");
+    static const int rk4[4] = {Z_RK4_0, Z_RK4_1, Z_RK4_2, Z_RK4_3};
+    static const int rk2[2] = {Z_RK2_0, Z_RK2_1};
+    const int ns = P->p.rk_order == 4 ? 4 : 2;
+    const int* modes = P->p.rk_order == 4 ? rk4 : rk2;
+    for (int it = 0; it < nsteps; ++it) {
+        for (int st = 0; st < ns; ++st) {
+            pst_status s = run_rhs_passes(P, st == 0 ? P->U : P->V, modes[st], nullptr);
+            if (s) return s;
+        }
+        P->steps++;
+    }
+    return PST_OK;
+}
+
+// --------------------------------------------------------------- diagnostics
+template <typename T>
+static void launch_energy(pst_plan* P, int c0, double* out) {
+    KTimer tm(P, PST_K_OTHER);
+    hipLaunchKernelGGL((k_energy_part<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, P->stream, (const cx<T>*)P->U,
+                       P->geo, c0, P->red);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(RED_THREADS), 0, P->stream, P->red, RED_BLOCKS, out, 0.5);
+}
+
+extern "C" pst_status pst_energy(pst_plan* P, double out[2]) {
+    if (!P || !out) return P ? fail(P, PST_ERR_INVALID_ARG, "out is NULL") : PST_ERR_INVALID_ARG;
+    double* res = P->red + RED_BLOCKS + MAX_SHELLS;
+    for (int grp = 0; grp < P->ncomp / 3; ++grp) {
+        if (P->p.precision == PST_FP64) launch_energy<double>(P, grp * 3, res + grp);
+        else launch_energy<float>(P, grp * 3, res + grp);
+    }
+    pst_status s = check_launch(P, "energy");
+    if (s) return s;
+    double h[2] = {0.0, 0.0};
+    HIPCHK(P, hipMemcpyAsync(h, res, sizeof(double) * (P->ncomp / 3), hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(P, hipStreamSynchronize(P->stream));
+    out[0] = h[0];
+    out[1] = P->ncomp == 6 ? h[1] : 0.0;
+    if (!isfinite(out[0]) || !isfinite(out[1])) return fail(P, PST_ERR_NONFINITE, "energy is not finite");
+    return PST_OK;
+}
+
+extern "C" pst_status pst_spectrum(pst_plan* P, int field, double* Ek, int nshells) {
+    if (!P) return PST_ERR_INVALID_ARG;
+    if (!Ek) return fail(P, PST_ERR_INVALID_ARG, "Ek is NULL");
+    if (!valid_field(P, field)) return fail(P, PST_ERR_INVALID_ARG, "field %d", field);
+    const int K = P->geo.K;
+    const int need = (int)floor(sqrt(3.0) * K + 0.5) + 1;
+    if (nshells < need || nshells > MAX_SHELLS)
+        return fail(P, PST_ERR_INVALID_ARG, "nshells must be in [%d, %d]", need, MAX_SHELLS);
+    double* bins = P->red + RED_BLOCKS;
+    HIPCHK(P, hipMemsetAsync(bins, 0, sizeof(double) * nshells, P->stream));
+    {
+        KTimer tm(P, PST_K_OTHER);
+        if (P->p.precision == PST_FP64)
+            hipLaunchKernelGGL((k_spectrum<double>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, P->stream,
+                               (const cx<double>*)P->U, P->geo, field * 3, bins, nshells);
+        else
+            hipLaunchKernelGGL((k_spectrum<float>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, P->stream,
+                               (const cx<float>*)P->U, P->geo, field * 3, bins, nshells);
+    }
+    pst_status s = check_launch(P, "spectrum");
+    if (s) return s;
+    HIPCHK(P, hipMemcpyAsync(Ek, bins, sizeof(double) * nshells, hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(P, hipStreamSynchronize(P->stream));
+    for (int i = 0; i < nshells; ++i)
+        if (!isfinite(Ek[i])) return fail(P, PST_ERR_NONFINITE, "spectrum is not finite");
+    return PST_OK;
+}
+
+// --------------------------------------------------------------- transforms
+extern "C" pst_status pst_fft_r2c(pst_plan* P, const void* in, void* out, int nfields) {
+    if (!P) return PST_ERR_INVALID_ARG;
+    if (!in || !out) return fail(P, PST_ERR_INVALID_ARG, "NULL buffer");
+    if (nfields < 1) return fail(P, PST_ERR_INVALID_ARG, "nfields < 1");
+    P->L->fft_r2c(P, in, out, nfields);
+    return check_launch(P, "fft_r2c");
+}
+
+extern "C" pst_status pst_fft_c2r(pst_plan* P, const void* in, void* out, int nfields) {
+    if (!P) return PST_ERR_INVALID_ARG;
+    if (!in || !out) return fail(P, PST_ERR_INVALID_ARG, "NULL buffer");
+    if (nfields < 1) return fail(P, PST_ERR_INVALID_ARG, "nfields < 1");
+    pst_status s = ensure_abi(P, abi_spec_bytes(P, nfields));
+    if (s) return s;
+    P->L->fft_c2r(P, in, out, nfields, P->abi);
+    return check_launch(P, "fft_c2r");
+}
+
+// --------------------------------------------------------------- timers
+extern "C" pst_status pst_timer_read(pst_plan* P, double* ms, long long* count, int reset) {
+    if (!P) return PST_ERR_INVALID_ARG;
+    if (!(P->p.flags & PST_FLAG_TIMERS)) return fail(P, PST_ERR_UNSUPPORTED, "plan created without PST_FLAG_TIMERS");
+    HIPCHK(P, hipStreamSynchronize(P->stream));
+    drain_timers(P);
+    for (int k = 0; k < PST_K_COUNT; ++k) {
+        if (ms) ms[k] = P->t_ms[k];
+        if (count) count[k] = P->t_cnt[k];
+        if (reset) {
+            P->t_ms[k] = 0.0;
+            P->t_cnt[k] = 0;
+        }
+    }
+    return PST_OK;
+}

@@ -97,44 +97,57 @@ def random_solenoidal(n, seed, field=0, spectrum=spectrum_c2, energy=1.0, kcut=N
     the other half is its complex conjugate, so the field is real.  |uhat| = A
     whatever the phases, so the amplitudes are rescaled to the requested
     energy 1/2 sum_k w |uhat|^2 (w = 1 on kx = 0, else 2) before the phases are
-    applied.
+    applied.  Built one kx plane at a time.
     """
     if kcut is None:
         kcut = kcut_23(n)
     nxh = n // 2 + 1
+    kxmax = min(kcut, n // 2)
     out = np.zeros((3, n, n, nxh), dtype)
     ks = np.arange(-kcut, kcut + 1)
-    kz, ky, kx = np.meshgrid(ks, ks, np.arange(0, min(kcut, n // 2) + 1), indexing="ij")
-    kz, ky, kx = kz.ravel(), ky.ravel(), kx.ravel()
-    canon = (kx > 0) | ((kx == 0) & ((ky > 0) | ((ky == 0) & (kz > 0))))
-    kx, ky, kz = kx[canon], ky[canon], kz[canon]
-    k2 = (kx * kx + ky * ky + kz * kz).astype(np.float64)
-    kmag = np.sqrt(k2)
-    amp2 = spectrum(kmag) / (4.0 * np.pi * k2)
+    kz2, ky2 = np.meshgrid(ks, ks, indexing="ij")
+    kz2, ky2 = kz2.ravel(), ky2.ravel()
+
+    def plane(kx):
+        if kx == 0:
+            keep = (ky2 > 0) | ((ky2 == 0) & (kz2 > 0))
+            return ky2[keep], kz2[keep]
+        return ky2, kz2
+
+    def amp2_of(kx, ky, kz):
+        k2 = (kx * kx + ky * ky + kz * kz).astype(np.float64)
+        return spectrum(np.sqrt(k2)) / (4.0 * np.pi * k2)
+
     # a canonical kx > 0 mode has weight 2; a canonical kx = 0 mode stands for
     # itself and its mirror, weight 1 each: every canonical mode counts twice
-    e_tot = 0.5 * np.sum(2.0 * amp2)
-    amp = np.sqrt(amp2 * (energy / e_tot)) if e_tot > 0 else np.zeros_like(amp2)
-    t1 = 2.0 * np.pi * uniform(seed, field, kx, ky, kz, 0)
-    t2 = 2.0 * np.pi * uniform(seed, field, kx, ky, kz, 1)
-    ph = 2.0 * np.pi * uniform(seed, field, kx, ky, kz, 2)
-    kvec = np.stack([kx, ky, kz]).astype(np.float64)
-    # e1 = k x zhat = (ky, -kx, 0), or xhat when k is parallel to zhat
-    e1 = np.stack([kvec[1], -kvec[0], np.zeros_like(kmag)])
-    par = (kx == 0) & (ky == 0)
-    e1[:, par] = np.array([1.0, 0.0, 0.0])[:, None]
-    e1 /= np.linalg.norm(e1, axis=0)
-    e2 = np.cross(kvec.T, e1.T).T
-    e2 /= np.linalg.norm(e2, axis=0)
-    coef = (np.exp(1j * t1) * np.cos(ph))[None] * e1 + (np.exp(1j * t2) * np.sin(ph))[None] * e2
-    coef *= amp[None]
-    iy = np.mod(ky, n)
-    iz = np.mod(kz, n)
-    for c in range(3):
-        out[c, iz, iy, kx] = coef[c]
-    m0 = kx == 0
-    for c in range(3):
-        out[c, np.mod(-kz[m0], n), np.mod(-ky[m0], n), 0] = np.conj(coef[c][m0])
+    e_tot = 0.0
+    for kx in range(kxmax + 1):
+        ky, kz = plane(kx)
+        e_tot += float(np.sum(amp2_of(kx, ky, kz)))
+    scale = energy / e_tot if e_tot > 0 else 0.0
+    for kx in range(kxmax + 1):
+        ky, kz = plane(kx)
+        kxa = np.full_like(ky, kx)
+        amp = np.sqrt(amp2_of(kx, ky, kz) * scale)
+        t1 = 2.0 * np.pi * uniform(seed, field, kxa, ky, kz, 0)
+        t2 = 2.0 * np.pi * uniform(seed, field, kxa, ky, kz, 1)
+        ph = 2.0 * np.pi * uniform(seed, field, kxa, ky, kz, 2)
+        kvec = np.stack([kxa, ky, kz]).astype(np.float64)
+        # e1 = k x zhat = (ky, -kx, 0), or xhat when k is parallel to zhat
+        e1 = np.stack([kvec[1], -kvec[0], np.zeros(ky.shape)])
+        par = (kxa == 0) & (ky == 0)
+        e1[:, par] = np.array([1.0, 0.0, 0.0])[:, None]
+        e1 /= np.sqrt(np.sum(e1 * e1, axis=0))
+        e2 = np.stack([kvec[1] * e1[2] - kvec[2] * e1[1], kvec[2] * e1[0] - kvec[0] * e1[2],
+                       kvec[0] * e1[1] - kvec[1] * e1[0]])
+        e2 /= np.sqrt(np.sum(e2 * e2, axis=0))
+        coef = (np.exp(1j * t1) * np.cos(ph))[None] * e1 + (np.exp(1j * t2) * np.sin(ph))[None] * e2
+        coef *= amp[None]
+        iy, iz = np.mod(ky, n), np.mod(kz, n)
+        for c in range(3):
+            out[c, iz, iy, kx] = coef[c]
+            if kx == 0:
+                out[c, np.mod(-kz, n), np.mod(-ky, n), 0] = np.conj(coef[c])
     return out
 
 

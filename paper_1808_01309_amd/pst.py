@@ -1,0 +1,241 @@
+"""ctypes binding over the C ABI of libpst.so (include/pst.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Importing this module loads libpst.so and raises ImportError if it is missing
+(build it with ``python -m paper_1808_01309_amd.build``); there is no fallback.
+
+Device buffers are passed as torch tensors (PyTorch provides device memory and
+the current HIP stream); host buffers as numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+# PyTorch ships its own HIP runtime (same soname as the system one).  Loading
+# torch first makes libpst.so bind to that runtime, so the process holds a
+# single HIP runtime and device pointers / streams from torch are valid here.
+import torch  # noqa: E402,F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpst.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: the HIP library has not been built")
+lib = ctypes.CDLL(LIB_PATH)
+
+# ------------------------------------------------------------------ ABI types
+PST_OK, PST_ERR_INVALID_ARG, PST_ERR_UNSUPPORTED_N, PST_ERR_OOM, PST_ERR_HIP, PST_ERR_NONFINITE, \
+    PST_ERR_UNSUPPORTED = range(7)
+PST_NS, PST_MHD = 0, 1
+PST_FP32, PST_FP64 = 0, 1
+PST_FIELD_U, PST_FIELD_B = 0, 1
+PST_SPACE_PHYS, PST_SPACE_SPEC = 0, 1
+PST_MEM_HOST, PST_MEM_DEVICE = 0, 1
+PST_FLAG_LINEAR_ONLY, PST_FLAG_TIMERS = 1, 2
+KERNEL_KINDS = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "fftx", "ffty", "fftz", "other"]
+
+
+class pst_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("solver", ctypes.c_int), ("precision", ctypes.c_int),
+                ("rk_order", ctypes.c_int), ("nu", ctypes.c_double), ("eta", ctypes.c_double),
+                ("dt", ctypes.c_double), ("dealias", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+class pst_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("kcut", ctypes.c_int), ("ncomp", ctypes.c_int),
+                ("modes_per_comp", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
+                ("radices", ctypes.c_int * 4), ("tile_lines", ctypes.c_int),
+                ("steps_done", ctypes.c_longlong)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_S = ctypes.c_int  # pst_status
+lib.pst_status_str.argtypes = [_S]
+lib.pst_status_str.restype = ctypes.c_char_p
+lib.pst_last_error.argtypes = [_P]
+lib.pst_last_error.restype = ctypes.c_char_p
+lib.pst_supported_n.argtypes = [_I]
+lib.pst_supported_n.restype = _I
+lib.pst_plan_create.argtypes = [ctypes.POINTER(pst_params), _P, ctypes.POINTER(_P)]
+lib.pst_plan_create.restype = _S
+lib.pst_plan_destroy.argtypes = [_P]
+lib.pst_plan_destroy.restype = None
+for _name, _args in [("pst_set_state", [_P, _I, _I, _P, _I]), ("pst_get_state", [_P, _I, _I, _P, _I]),
+                     ("pst_set_forcing", [_P, _P, _I]), ("pst_rhs", [_P, _P, _P]), ("pst_step", [_P, _I]),
+                     ("pst_energy", [_P, _P]), ("pst_spectrum", [_P, _I, _P, _I]),
+                     ("pst_fft_r2c", [_P, _P, _P, _I]), ("pst_fft_c2r", [_P, _P, _P, _I]),
+                     ("pst_query", [_P, ctypes.POINTER(pst_info)]),
+                     ("pst_timer_read", [_P, _P, _P, _I])]:
+    getattr(lib, _name).argtypes = _args
+    getattr(lib, _name).restype = _S
+
+EXPORTED = ["pst_status_str", "pst_last_error", "pst_supported_n", "pst_plan_create", "pst_plan_destroy",
+            "pst_set_state", "pst_get_state", "pst_set_forcing", "pst_rhs", "pst_step", "pst_energy",
+            "pst_spectrum", "pst_fft_r2c", "pst_fft_c2r", "pst_query", "pst_timer_read"]
+
+
+class PstError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{lib.pst_status_str(status).decode()}: {msg}")
+        self.status = status
+
+
+def kcut_23(n):
+    return -(-n // 3) - 1
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _ptr(x):
+    """Device pointer of a torch tensor, or host pointer of a numpy array."""
+    if x is None:
+        return None, PST_MEM_HOST
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("host array must be C-contiguous")
+        return ctypes.c_void_p(x.ctypes.data), PST_MEM_HOST
+    if not x.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(x.data_ptr()), (PST_MEM_DEVICE if x.is_cuda else PST_MEM_HOST)
+
+
+class Plan:
+    """One solver plan (pst_plan_create ... pst_plan_destroy)."""
+
+    def __init__(self, n, solver="ns", precision="fp32", rk_order=4, nu=0.0, eta=None, dt=1e-3,
+                 linear_only=False, timers=False, stream=None):
+        p = pst_params(n=n, solver=PST_MHD if solver == "mhd" else PST_NS,
+                       precision=PST_FP64 if precision == "fp64" else PST_FP32, rk_order=rk_order,
+                       nu=nu, eta=nu if eta is None else eta, dt=dt, dealias=0,
+                       flags=(PST_FLAG_LINEAR_ONLY if linear_only else 0) | (PST_FLAG_TIMERS if timers else 0))
+        self.params = p
+        self.n = n
+        self.fp64 = precision == "fp64"
+        self.mhd = solver == "mhd"
+        self.ncomp = 6 if self.mhd else 3
+        self.real_np = np.float64 if self.fp64 else np.float32
+        self.cplx_np = np.complex128 if self.fp64 else np.complex64
+        h = _P()
+        s = lib.pst_plan_create(ctypes.byref(p), _P(_stream_handle(stream)), ctypes.byref(h))
+        if s != PST_OK:
+            raise PstError(s, lib.pst_last_error(None).decode())
+        self._h = h
+
+    # --------------------------------------------------------------- helpers
+    def _check(self, s):
+        if s != PST_OK:
+            raise PstError(s, lib.pst_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pst_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def spec_shape(self, ncomp=3):
+        return (ncomp, self.n, self.n, self.n // 2 + 1)
+
+    def phys_shape(self, ncomp=3):
+        return (ncomp, self.n, self.n, self.n)
+
+    # --------------------------------------------------------------- ABI calls
+    def set_state(self, data, field="u", space=None):
+        """data: numpy (host) or torch (device) array, spectral complex
+        [3][n][n][n/2+1] or physical real [3][n][n][n]."""
+        f = PST_FIELD_B if field == "b" else PST_FIELD_U
+        if space is None:
+            space = "spec" if np.iscomplexobj(np.empty(0, dtype=_np_dtype(data))) else "phys"
+        if isinstance(data, np.ndarray):
+            data = np.ascontiguousarray(data, self.cplx_np if space == "spec" else self.real_np)
+        ptr, mem = _ptr(data)
+        self._check(lib.pst_set_state(self._h, f, PST_SPACE_SPEC if space == "spec" else PST_SPACE_PHYS,
+                                      ptr, mem))
+
+    def get_state(self, field="u", space="spec", out=None):
+        f = PST_FIELD_B if field == "b" else PST_FIELD_U
+        sp = PST_SPACE_SPEC if space == "spec" else PST_SPACE_PHYS
+        if out is None:
+            out = np.empty(self.spec_shape() if space == "spec" else self.phys_shape(),
+                           self.cplx_np if space == "spec" else self.real_np)
+        ptr, mem = _ptr(out)
+        self._check(lib.pst_get_state(self._h, f, sp, ptr, mem))
+        return out
+
+    def set_forcing(self, fhat):
+        if fhat is None:
+            self._check(lib.pst_set_forcing(self._h, None, PST_MEM_HOST))
+            return
+        if isinstance(fhat, np.ndarray):
+            fhat = np.ascontiguousarray(fhat, self.cplx_np)
+        ptr, mem = _ptr(fhat)
+        self._check(lib.pst_set_forcing(self._h, ptr, mem))
+
+    def rhs(self, state_dev, rhs_dev):
+        a, _ = _ptr(state_dev)
+        b, _ = _ptr(rhs_dev)
+        self._check(lib.pst_rhs(self._h, a, b))
+
+    def step(self, nsteps=1):
+        self._check(lib.pst_step(self._h, nsteps))
+
+    def energy(self):
+        out = np.zeros(2, np.float64)
+        self._check(lib.pst_energy(self._h, out.ctypes.data_as(_P)))
+        return float(out[0]), float(out[1])
+
+    def spectrum(self, field="u", nshells=None):
+        if nshells is None:
+            nshells = int(np.floor(np.sqrt(3.0) * kcut_23(self.n) + 0.5)) + 1
+        out = np.zeros(nshells, np.float64)
+        self._check(lib.pst_spectrum(self._h, PST_FIELD_B if field == "b" else PST_FIELD_U,
+                                     out.ctypes.data_as(_P), nshells))
+        return out
+
+    def fft_r2c(self, x, out, nfields):
+        a, _ = _ptr(x)
+        b, _ = _ptr(out)
+        self._check(lib.pst_fft_r2c(self._h, a, b, nfields))
+
+    def fft_c2r(self, x, out, nfields):
+        a, _ = _ptr(x)
+        b, _ = _ptr(out)
+        self._check(lib.pst_fft_c2r(self._h, a, b, nfields))
+
+    def query(self):
+        info = pst_info()
+        self._check(lib.pst_query(self._h, ctypes.byref(info)))
+        return {"n": info.n, "kcut": info.kcut, "ncomp": info.ncomp,
+                "modes_per_comp": info.modes_per_comp, "workspace_bytes": info.workspace_bytes,
+                "radices": [r for r in info.radices if r], "tile_lines": info.tile_lines,
+                "steps_done": info.steps_done}
+
+    def timers(self, reset=True):
+        ms = np.zeros(len(KERNEL_KINDS), np.float64)
+        cnt = np.zeros(len(KERNEL_KINDS), np.int64)
+        self._check(lib.pst_timer_read(self._h, ms.ctypes.data_as(_P), cnt.ctypes.data_as(_P), int(reset)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def _np_dtype(x):
+    if isinstance(x, np.ndarray):
+        return x.dtype
+    import torch
+    return {torch.complex64: np.complex64, torch.complex128: np.complex128,
+            torch.float32: np.float32, torch.float64: np.float64}[x.dtype]
