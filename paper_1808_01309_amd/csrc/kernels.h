@@ -42,6 +42,37 @@ template <typename T, bool MHD, int N>
 constexpr int xpass_lines() { return tile_lines<T>() / (MHD ? 2 : 1) / (N >= 1024 ? 2 : 1); }
 constexpr int LINE_BLOCK = 256;
 
+// A kernel configuration: radix schedule P (length N), G threads per line,
+// TL lines per tile of the strided passes.
+template <class P_, int G_, int TL_>
+struct KCfg {
+    using P = P_;
+    static constexpr int N = P_::N, G = G_, TL = TL_;
+};
+template <typename T, int N> using LineCfg = KCfg<typename NCfg<N>::P, NCfg<N>::G, 1>;
+template <typename T, int N> using TileCfg = KCfg<typename NCfg<N>::P, NCfg<N>::G, tile_lines<T>()>;
+template <typename T, int N, bool MHD>
+using XCfg = KCfg<typename NCfg<N>::P, NCfg<N>::G, xpass_lines<T, MHD, N>()>;
+
+// LDS elements a body needs for a block of NT threads.
+template <typename T, class CF, int NT> constexpr int line_lds() { return (NT / CF::G) * LineLds<T>::size(CF::N); }
+template <typename T, class CF, int NT> constexpr int tile_lds() { return (NT / (CF::G * CF::TL)) * CF::N * (CF::TL + 1); }
+template <int N, int TL> constexpr int ztiles() { return (N + TL - 1) / TL; }
+
+// Work units: a line body handles NT / G lines per unit, a tile body
+// NT / (G TL) tiles per unit.
+template <class CF, int NT> inline int64_t line_units(const Geo& g) {
+    return ((int64_t)g.nxk * g.M + NT / CF::G - 1) / (NT / CF::G);
+}
+template <class CF, int NT> inline int64_t ytile_units(const Geo& g, int nf) {
+    constexpr int SG = NT / (CF::G * CF::TL);
+    return ((int64_t)nf * g.nxk * ztiles<CF::N, CF::TL>() + SG - 1) / SG;
+}
+template <class CF, int NT> inline int64_t xtile_units() {
+    constexpr int SG = NT / (CF::G * CF::TL);
+    return ((int64_t)CF::N * ztiles<CF::N, CF::TL>() + SG - 1) / SG;
+}
+
 template <typename T>
 struct RkArgs {
     cx<T>* U;          // u_n (compact)
@@ -59,15 +90,15 @@ struct RkArgs {
 // ------------------------------------------------------------ zinv + curl
 // One line (kx, jy) per G threads.  NGRP = 1 (u) or 2 (u, b): each group of
 // 3 state components yields 6 fields: v and i k x v.
-template <typename T, int N, int NGRP>
-__global__ __launch_bounds__(LINE_BLOCK) void k_zinv(const cx<T>* __restrict__ st, cx<T>* __restrict__ A,
-                                                      const cx<T>* __restrict__ tw, Geo geo) {
-    using C = NCfg<N>;
-    using F = Fft<T, typename C::P, C::G, true>;
-    constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N);
-    __shared__ cx<T> sm[LPB * LS];
-    const int l = threadIdx.x / G, g = threadIdx.x % G;
-    const int64_t line = (int64_t)blockIdx.x * LPB + l;
+template <typename T, class CF, int NT, int NGRP>
+__device__ __forceinline__ void zinv_body(const cx<T>* __restrict__ st, cx<T>* __restrict__ A,
+                                          const cx<T>* __restrict__ tw, const Geo& geo, int64_t unit, int tid,
+                                          cx<T>* sm) {
+    constexpr int N = CF::N, G = CF::G;
+    using F = Fft<T, typename CF::P, G, true>;
+    constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
+    const int l = tid / G, g = tid % G;
+    const int64_t line = unit * LPB + l;
     const bool active = line < (int64_t)geo.nxk * geo.M;
     const int kx = active ? (int)(line / geo.M) : 0;
     const int jy = active ? (int)(line % geo.M) : 0;
@@ -75,57 +106,68 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_zinv(const cx<T>* __restrict__ s
     const LineLds<T> lds{sm + l * LS};
     const int64_t lin = (int64_t)kx * geo.M + jy;
     for (int grp = 0; grp < NGRP; ++grp) {
-        cx<T> u[3][E], w[3][E];
+        const cx<T>* src = st + (int64_t)(grp * 3) * geo.sc + lin * geo.M;
+        // pass 1: the three components of v; pass 2: i k x v from the same
+        // (now cache-resident) line, so only 3 lines live in registers
+#pragma nounroll
+        for (int half = 0; half < 2; ++half) {
+            cx<T> u[3][E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int p = F::first_pos(g, e);
-            const int j = j_of_pos(p, geo);
-            const T fkz = T(k_of_pos(p, N));
+            for (int e = 0; e < E; ++e) {
+                const int j = j_of_pos(F::first_pos(g, e), geo);
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                u[c][e] = (active && j >= 0) ? st[(grp * 3 + c) * geo.sc + lin * geo.M + j] : czero<T>();
-            // w = i k x u
-            w[0][e] = mul_i(cx<T>{fky * u[2][e].x - fkz * u[1][e].x, fky * u[2][e].y - fkz * u[1][e].y});
-            w[1][e] = mul_i(cx<T>{fkz * u[0][e].x - fkx * u[2][e].x, fkz * u[0][e].y - fkx * u[2][e].y});
-            w[2][e] = mul_i(cx<T>{fkx * u[1][e].x - fky * u[0][e].x, fkx * u[1][e].y - fky * u[0][e].y});
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            F::run(u[c], g, lds, tw);
-            if (active) {
-                cx<T>* dst = A + (int64_t)(grp * 6 + c) * geo.sa + lin * N;
-#pragma unroll
-                for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = u[c][e];
+                for (int c = 0; c < 3; ++c) u[c][e] = (active && j >= 0) ? src[c * geo.sc + j] : czero<T>();
             }
-        }
+            if (half == 1) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            F::run(w[c], g, lds, tw);
-            if (active) {
-                cx<T>* dst = A + (int64_t)(grp * 6 + 3 + c) * geo.sa + lin * N;
+                for (int e = 0; e < E; ++e) {
+                    const T fkz = T(k_of_pos(F::first_pos(g, e), N));
+                    const cx<T> a = u[0][e], b = u[1][e], c = u[2][e];
+                    u[0][e] = mul_i(cx<T>{fky * c.x - fkz * b.x, fky * c.y - fkz * b.y});
+                    u[1][e] = mul_i(cx<T>{fkz * a.x - fkx * c.x, fkz * a.y - fkx * c.y});
+                    u[2][e] = mul_i(cx<T>{fkx * b.x - fky * a.x, fkx * b.y - fky * a.y});
+                }
+            }
 #pragma unroll
-                for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = w[c][e];
+            for (int c = 0; c < 3; ++c) {
+                F::run(u[c], g, lds, tw);
+                if (active) {
+                    cx<T>* dst = A + (int64_t)(grp * 6 + half * 3 + c) * geo.sa + lin * N;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = u[c][e];
+                }
             }
         }
     }
 }
 
+template <typename T, class CF, int NGRP>
+__global__ __launch_bounds__(LINE_BLOCK) void k_zinv(const cx<T>* __restrict__ st, cx<T>* __restrict__ A,
+                                                      const cx<T>* __restrict__ tw, Geo geo) {
+    __shared__ cx<T> sm[line_lds<T, CF, LINE_BLOCK>()];
+    zinv_body<T, CF, LINE_BLOCK, NGRP>(st, A, tw, geo, blockIdx.x, threadIdx.x, sm);
+}
+
 // ------------------------------------------------------------ y passes
 // Tile of TL consecutive z for one (field, kx).  INV: rows = kept ky (M) ->
-// all y (N); forward: all y -> kept ky.
-template <typename T, int N, bool INV>
-__global__ __launch_bounds__(NCfg<N>::G * tile_lines<T>()) void k_ypass(const cx<T>* __restrict__ in,
-                                                                        cx<T>* __restrict__ out,
-                                                                        const cx<T>* __restrict__ tw, Geo geo,
-                                                                        int64_t fs_in, int64_t fs_out) {
-    using C = NCfg<N>;
-    using F = Fft<T, typename C::P, C::G, INV>;
-    constexpr int G = C::G, E = F::E, TL = tile_lines<T>(), TLP = TL + 1;
-    __shared__ cx<T> sm[N * TLP];
-    const int t = threadIdx.x % TL, g = threadIdx.x / TL;
-    const int z = blockIdx.x * TL + t;
-    const bool zin = z < N;
-    const int kx = blockIdx.y, f = blockIdx.z;
+// all y (N); forward: all y -> kept ky.  A block of NT threads runs
+// NT / (G TL) tiles side by side.
+template <typename T, class CF, int NT, bool INV>
+__device__ __forceinline__ void ypass_body(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                           const cx<T>* __restrict__ tw, const Geo& geo, int64_t fs_in,
+                                           int64_t fs_out, int nf, int64_t unit, int tid, cx<T>* sm) {
+    constexpr int N = CF::N, G = CF::G, TL = CF::TL, TLP = TL + 1, TT = G * TL, SG = NT / TT;
+    using F = Fft<T, typename CF::P, G, INV>;
+    constexpr int E = F::E, NTZ = ztiles<N, TL>();
+    const int s = tid / TT, r = tid % TT;
+    const int t = r % TL, g = r / TL;
+    const int64_t tile = unit * SG + s;
+    const bool valid = tile < (int64_t)nf * geo.nxk * NTZ;
+    const int zt = valid ? (int)(tile % NTZ) : 0;
+    const int64_t rest = valid ? tile / NTZ : 0;
+    const int kx = (int)(rest % geo.nxk), f = (int)(rest / geo.nxk);
+    const int z = zt * TL + t;
+    const bool zin = valid && z < N;
     const int rows_in = INV ? geo.M : N, rows_out = INV ? N : geo.M;
     const cx<T>* src = in + f * fs_in + (int64_t)kx * rows_in * N + z;
     cx<T>* dst = out + f * fs_out + (int64_t)kx * rows_out * N + z;
@@ -136,7 +178,7 @@ __global__ __launch_bounds__(NCfg<N>::G * tile_lines<T>()) void k_ypass(const cx
         const int row = INV ? j_of_pos(p, geo) : p;
         v[e] = (zin && row >= 0) ? src[(int64_t)row * N] : czero<T>();
     }
-    F::run(v, g, TileLds<T, TLP>{sm + t}, tw);
+    F::run(v, g, TileLds<T, TLP>{sm + s * N * TLP + t}, tw);
     if (zin) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -147,28 +189,39 @@ __global__ __launch_bounds__(NCfg<N>::G * tile_lines<T>()) void k_ypass(const cx
     }
 }
 
+template <typename T, class CF, bool INV>
+__global__ __launch_bounds__((CF::G * CF::TL)) void k_ypass(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                          const cx<T>* __restrict__ tw, Geo geo, int64_t fs_in,
+                                                          int64_t fs_out, int nf) {
+    __shared__ cx<T> sm[tile_lds<T, CF, CF::G * CF::TL>()];
+    ypass_body<T, CF, CF::G * CF::TL, INV>(in, out, tw, geo, fs_in, fs_out, nf, blockIdx.x, threadIdx.x, sm);
+}
+
 // ------------------------------------------------------------ fused x pass
 // Tile of TL consecutive z at one y.  Backward x for the field pairs
 // (v, i k x v) packed as one complex line each (two real transforms for the
 // price of one), cross products in registers, forward x of the products
 // packed two per complex line, split by Hermitian symmetry, kx <= K kept.
-template <typename T, int N, bool MHD>
-__global__ __launch_bounds__((NCfg<N>::G * xpass_lines<T, MHD, N>())) void k_xpass(const cx<T>* __restrict__ Bf,
-                                                                        cx<T>* __restrict__ Cf,
-                                                                        const cx<T>* __restrict__ tw, Geo geo) {
-    using C = NCfg<N>;
-    using FI = Fft<T, typename C::P, C::G, true, false>;
-    using FF = Fft<T, typename C::P, C::G, false, true>;
-    constexpr int G = C::G, E = FI::E, TL = xpass_lines<T, MHD, N>(), TLP = TL + 1;
+template <typename T, class CF, int NT, bool MHD>
+__device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
+                                           const cx<T>* __restrict__ tw, const Geo& geo, int64_t unit, int tid,
+                                           cx<T>* sm) {
+    constexpr int N = CF::N, G = CF::G, TL = CF::TL, TLP = TL + 1, TT = G * TL, SG = NT / TT;
+    using FI = Fft<T, typename CF::P, G, true, false>;
+    using FF = Fft<T, typename CF::P, G, false, true>;
+    constexpr int E = FI::E, NTZ = ztiles<N, TL>();
     constexpr int NP = MHD ? 6 : 3;   // backward pairs
     constexpr int NO = MHD ? 3 : 2;   // forward packed lines
     constexpr int NOUT = MHD ? 6 : 3; // output fields
-    __shared__ cx<T> sm[N * TLP];
-    const TileLds<T, TLP> lds{sm + threadIdx.x % TL};
-    const int t = threadIdx.x % TL, g = threadIdx.x / TL;
-    const int z = blockIdx.x * TL + t;
-    const bool zin = z < N;
-    const int y = blockIdx.y;
+    const int s = tid / TT, r = tid % TT;
+    const int t = r % TL, g = r / TL;
+    const int64_t tile = unit * SG + s;
+    const bool valid = tile < (int64_t)N * NTZ;
+    const int zt = valid ? (int)(tile % NTZ) : 0;
+    const int y = valid ? (int)(tile / NTZ) : 0;
+    const int z = zt * TL + t;
+    const bool zin = valid && z < N;
+    const TileLds<T, TLP> lds{sm + s * N * TLP + t};
     const int64_t nn = (int64_t)N * N;
     const int64_t off = (int64_t)y * N + z;
     const int K = geo.K;
@@ -237,6 +290,13 @@ __global__ __launch_bounds__((NCfg<N>::G * xpass_lines<T, MHD, N>())) void k_xpa
     }
 }
 
+template <typename T, class CF, bool MHD>
+__global__ __launch_bounds__((CF::G * CF::TL)) void k_xpass(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
+                                                          const cx<T>* __restrict__ tw, Geo geo) {
+    __shared__ cx<T> sm[tile_lds<T, CF, CF::G * CF::TL>()];
+    xpass_body<T, CF, CF::G * CF::TL, MHD>(Bf, Cf, tw, geo, blockIdx.x, threadIdx.x, sm);
+}
+
 // ------------------------------------------------------------ zfwd + update
 template <typename T>
 __device__ __forceinline__ void rk_apply(int mode, const RkArgs<T>& a, int grp, int64_t idx, int k2, cx<T> nk) {
@@ -278,16 +338,15 @@ __device__ __forceinline__ void rk_apply(int mode, const RkArgs<T>& a, int grp, 
     }
 }
 
-template <typename T, int N, bool MHD>
-__global__ __launch_bounds__(LINE_BLOCK) void k_zfwd(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw,
-                                                      Geo geo, RkArgs<T> ra, int mode) {
-    using C = NCfg<N>;
-    using F = Fft<T, typename C::P, C::G, false>;
-    constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N);
+template <typename T, class CF, int NT, bool MHD>
+__device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw, const Geo& geo,
+                                          const RkArgs<T>& ra, int mode, int64_t unit, int tid, cx<T>* sm) {
+    constexpr int N = CF::N, G = CF::G;
+    using F = Fft<T, typename CF::P, G, false>;
+    constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
     constexpr int NF = MHD ? 6 : 3;
-    __shared__ cx<T> sm[LPB * LS];
-    const int l = threadIdx.x / G, g = threadIdx.x % G;
-    const int64_t line = (int64_t)blockIdx.x * LPB + l;
+    const int l = tid / G, g = tid % G;
+    const int64_t line = unit * LPB + l;
     const bool active = line < (int64_t)geo.nxk * geo.M;
     const int kx = active ? (int)(line / geo.M) : 0;
     const int jy = active ? (int)(line % geo.M) : 0;
@@ -349,6 +408,13 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_zfwd(const cx<T>* __restrict__ D
             for (int c = 0; c < 3; ++c) rk_apply(mode, ra, 1, (3 + c) * geo.sc + idx, k2, b[c]);
         }
     }
+}
+
+template <typename T, class CF, bool MHD>
+__global__ __launch_bounds__(LINE_BLOCK) void k_zfwd(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw,
+                                                      Geo geo, RkArgs<T> ra, int mode) {
+    __shared__ cx<T> sm[line_lds<T, CF, LINE_BLOCK>()];
+    zfwd_body<T, CF, LINE_BLOCK, MHD>(D, tw, geo, ra, mode, blockIdx.x, threadIdx.x, sm);
 }
 
 // ------------------------------------------------------------ standalone FFTs
@@ -464,39 +530,48 @@ struct Impl {
     static constexpr int TL = tile_lines<T>();
     static constexpr int TB = C::G * TL;
 
+    using LC = LineCfg<T, N>;
+    using TC = TileCfg<T, N>;
+
     static void zinv(pst_plan* P, const void* st) {
         KTimer tm(P, PST_K_ZINV);
         const Geo& g = P->geo;
-        unsigned nb = cdiv((int64_t)g.nxk * g.M, LINE_BLOCK / C::G);
+        const unsigned nb = (unsigned)line_units<LC, LINE_BLOCK>(g);
         if (P->ncomp == 6)
-            hipLaunchKernelGGL((k_zinv<T, N, 2>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
+            hipLaunchKernelGGL((k_zinv<T, LC, 2>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
                                (cx<T>*)P->A, (const cx<T>*)P->tw, g);
         else
-            hipLaunchKernelGGL((k_zinv<T, N, 1>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
+            hipLaunchKernelGGL((k_zinv<T, LC, 1>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
                                (cx<T>*)P->A, (const cx<T>*)P->tw, g);
     }
     static void yinv(pst_plan* P) {
         KTimer tm(P, PST_K_YINV);
         const Geo& g = P->geo;
-        hipLaunchKernelGGL((k_ypass<T, N, true>), dim3(cdiv(N, TL), g.nxk, P->nfin), dim3(TB), 0, P->stream,
-                           (const cx<T>*)P->A, (cx<T>*)P->B, (const cx<T>*)P->tw, g, g.sa, g.sb);
+        const unsigned nb = (unsigned)ytile_units<TC, TC::G * TC::TL>(g, P->nfin);
+        hipLaunchKernelGGL((k_ypass<T, TC, true>), dim3(nb), dim3(TC::G * TC::TL), 0, P->stream,
+                           (const cx<T>*)P->A, (cx<T>*)P->B, (const cx<T>*)P->tw, g, g.sa, g.sb, P->nfin);
     }
     static void xpass(pst_plan* P) {
         KTimer tm(P, PST_K_XPASS);
         const Geo& g = P->geo;
-        constexpr int TLM = xpass_lines<T, true, N>(), TLN = xpass_lines<T, false, N>();
-        if (P->ncomp == 6)
-            hipLaunchKernelGGL((k_xpass<T, N, true>), dim3(cdiv(N, TLM), N), dim3(C::G * TLM), 0, P->stream,
-                               (const cx<T>*)P->B, (cx<T>*)P->C, (const cx<T>*)P->tw, g);
-        else
-            hipLaunchKernelGGL((k_xpass<T, N, false>), dim3(cdiv(N, TLN), N), dim3(C::G * TLN), 0, P->stream,
-                               (const cx<T>*)P->B, (cx<T>*)P->C, (const cx<T>*)P->tw, g);
+        if (P->ncomp == 6) {
+            using XC = XCfg<T, N, true>;
+            hipLaunchKernelGGL((k_xpass<T, XC, true>), dim3((unsigned)xtile_units<XC, XC::G * XC::TL>()),
+                               dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
+                               (const cx<T>*)P->tw, g);
+        } else {
+            using XC = XCfg<T, N, false>;
+            hipLaunchKernelGGL((k_xpass<T, XC, false>), dim3((unsigned)xtile_units<XC, XC::G * XC::TL>()),
+                               dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
+                               (const cx<T>*)P->tw, g);
+        }
     }
     static void yfwd(pst_plan* P) {
         KTimer tm(P, PST_K_YFWD);
         const Geo& g = P->geo;
-        hipLaunchKernelGGL((k_ypass<T, N, false>), dim3(cdiv(N, TL), g.nxk, P->nfout), dim3(TB), 0, P->stream,
-                           (const cx<T>*)P->C, (cx<T>*)P->A, (const cx<T>*)P->tw, g, g.sb, g.sa);
+        const unsigned nb = (unsigned)ytile_units<TC, TC::G * TC::TL>(g, P->nfout);
+        hipLaunchKernelGGL((k_ypass<T, TC, false>), dim3(nb), dim3(TC::G * TC::TL), 0, P->stream,
+                           (const cx<T>*)P->C, (cx<T>*)P->A, (const cx<T>*)P->tw, g, g.sb, g.sa, P->nfout);
     }
     static void zfwd(pst_plan* P, int mode, void* rhs_out) {
         KTimer tm(P, PST_K_ZFWD);
@@ -514,12 +589,12 @@ struct Impl {
         ra.F = (const cx<T>*)P->force;
         ra.kf = P->kf;
         ra.lin_only = (P->p.flags & PST_FLAG_LINEAR_ONLY) ? 1 : 0;
-        unsigned nb = cdiv((int64_t)g.nxk * g.M, LINE_BLOCK / C::G);
+        const unsigned nb = (unsigned)line_units<LC, LINE_BLOCK>(g);
         if (P->ncomp == 6)
-            hipLaunchKernelGGL((k_zfwd<T, N, true>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+            hipLaunchKernelGGL((k_zfwd<T, LC, true>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
                                (const cx<T>*)P->tw, g, ra, mode);
         else
-            hipLaunchKernelGGL((k_zfwd<T, N, false>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+            hipLaunchKernelGGL((k_zfwd<T, LC, false>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
                                (const cx<T>*)P->tw, g, ra, mode);
     }
     static void fft_r2c(pst_plan* P, const void* in, void* out, int nf) {

@@ -152,9 +152,13 @@ def random_solenoidal(n, seed, field=0, spectrum=spectrum_c2, energy=1.0, kcut=N
 
 
 def forcing_shells(n, seed, lo=2, hi=3, energy=1.0, kcut=None, dtype=np.complex128):
-    """Constant solenoidal random-phase forcing on shells lo..hi (seed + 1)."""
+    """Constant solenoidal random-phase forcing on shells lo..hi (seed + 1).
+    Only the box |k_i| <= hi + 1 can hold those shells, so only it is drawn
+    (the draws are keyed by mode, so the result does not depend on the box)."""
+    if kcut is None:
+        kcut = kcut_23(n)
     return random_solenoidal(n, seed + 1, field=7, spectrum=flat_shells(lo, hi),
-                             energy=energy, kcut=kcut, dtype=dtype)
+                             energy=energy, kcut=min(kcut, hi + 1), dtype=dtype)
 
 
 # ------------------------------------------------------------ analytic fields
