@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fft", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counter scaling)")
     return ap.parse_args()
 
 
@@ -159,6 +161,12 @@ def main():
     from paper_1808_01309_amd import pst
 
     n = a.n
+    if a.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] n={n} fp32 solver: warmup {a.warmup}, timed {a.steps}", file=sys.stderr, flush=True)
     ms32, tm32, e32, info = run_solver(pst, torch, I, n, "fp32", a.steps, a.warmup)
     out_extra = {"fp32": {"ms_per_step": ms32, "energy_end": e32}}

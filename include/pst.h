@@ -183,6 +183,59 @@ pst_status pst_query(const pst_plan *plan, pst_info *info);
  * launch.  Without the flag: UNSUPPORTED. */
 pst_status pst_timer_read(pst_plan *plan, double *ms, long long *count, int reset);
 
+/* ------------------------------------------------------------------------
+ * Ensembles: many independent Navier-Stokes runs of uneven n advanced
+ * together.  This batches what the paper batches over CUDA streams (Sec. 3.3:
+ * many small transforms in flight at once) but keeps every run resident on
+ * the device and advances all of them with one persistent kernel launch per
+ * time step (device-wide barriers between the transform passes), replayed
+ * from a captured HIP graph.
+ * ---------------------------------------------------------------------- */
+typedef struct pst_ensemble pst_ensemble;
+
+enum {
+    PST_ENS_PERSISTENT_GRAPH = 0, /* persistent step kernel replayed from a HIP graph (default) */
+    PST_ENS_PERSISTENT = 1,       /* persistent step kernel, launched directly */
+    PST_ENS_BATCHED = 2,          /* one launch per (pass, grid size) covering all runs of that size */
+    PST_ENS_SEQUENTIAL = 3        /* one launch per (pass, run) */
+};
+
+/* Create nruns runs; run r has grid n[r] (each of 32, 48, 64, 96; at most 4
+ * distinct sizes) and the parameters in common (solver NS, precision FP32,
+ * rk_order 2 or 4, nu, dt; flags 0).  States start at zero.  hip_stream is
+ * borrowed.  Errors: INVALID_ARG, UNSUPPORTED_N, UNSUPPORTED, OOM, HIP. */
+pst_status pst_ensemble_create(int nruns, const int *n, const pst_params *common, void *hip_stream,
+                               pst_ensemble **out);
+void pst_ensemble_destroy(pst_ensemble *ens);
+const char *pst_ensemble_last_error(const pst_ensemble *ens);
+
+/* State of run `run`: complex float [3][n][n][n/2+1] spectral layout of
+ * pst_set_state (dealiased, kx = 0 plane made Hermitian).  HOST copies are
+ * synchronous, DEVICE copies stream-ordered. */
+pst_status pst_ensemble_set_state(pst_ensemble *ens, int run, const void *uhat, int mem);
+pst_status pst_ensemble_get_state(pst_ensemble *ens, int run, void *uhat, int mem);
+
+/* Advance every run by nsteps steps in the current mode; the persistent modes
+ * synchronise the stream and return HIP if a device-wide barrier timed out. */
+pst_status pst_ensemble_step(pst_ensemble *ens, int nsteps);
+pst_status pst_ensemble_set_mode(pst_ensemble *ens, int mode);
+
+/* Energy of every run (double[nruns]).  Synchronous. */
+pst_status pst_ensemble_energy(pst_ensemble *ens, double *per_run);
+
+/* Pick the schedule variant (radix order x tile lines) by timing each on
+ * persistent steps (the state is saved and restored around the timing).
+ * cache_path (may be NULL) is a JSON object keyed by device architecture,
+ * precision, RK order and the run sizes; a cached choice is reused unless
+ * force != 0.  *chosen (may be NULL) receives the variant. */
+pst_status pst_ensemble_autotune(pst_ensemble *ens, const char *cache_path, int force, int *chosen);
+pst_status pst_ensemble_set_schedule(pst_ensemble *ens, int variant);
+
+/* Distinct sizes (ascending), runs per size, current variant and persistent
+ * grid size.  Arrays need room for 4 entries; any pointer may be NULL. */
+pst_status pst_ensemble_query(const pst_ensemble *ens, int *nclasses, int *class_n, int *class_runs,
+                              int *variant, int *grid);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,7 +72,23 @@ for _name, _args in [("pst_set_state", [_P, _I, _I, _P, _I]), ("pst_get_state", 
     getattr(lib, _name).argtypes = _args
     getattr(lib, _name).restype = _S
 
-EXPORTED = ["pst_status_str", "pst_last_error", "pst_supported_n", "pst_plan_create", "pst_plan_destroy",
+_ens_sigs = [("pst_ensemble_create", [_I, _P, ctypes.POINTER(pst_params), _P, ctypes.POINTER(_P)]),
+             ("pst_ensemble_set_state", [_P, _I, _P, _I]), ("pst_ensemble_get_state", [_P, _I, _P, _I]),
+             ("pst_ensemble_step", [_P, _I]), ("pst_ensemble_set_mode", [_P, _I]),
+             ("pst_ensemble_energy", [_P, _P]), ("pst_ensemble_autotune", [_P, ctypes.c_char_p, _I, _P]),
+             ("pst_ensemble_set_schedule", [_P, _I]), ("pst_ensemble_query", [_P, _P, _P, _P, _P, _P])]
+for _name, _args in _ens_sigs:
+    getattr(lib, _name).argtypes = _args
+    getattr(lib, _name).restype = _S
+lib.pst_ensemble_destroy.argtypes = [_P]
+lib.pst_ensemble_destroy.restype = None
+lib.pst_ensemble_last_error.argtypes = [_P]
+lib.pst_ensemble_last_error.restype = ctypes.c_char_p
+
+EXPORTED = ["pst_ensemble_create", "pst_ensemble_destroy", "pst_ensemble_last_error", "pst_ensemble_set_state",
+            "pst_ensemble_get_state", "pst_ensemble_step", "pst_ensemble_set_mode", "pst_ensemble_energy",
+            "pst_ensemble_autotune", "pst_ensemble_set_schedule", "pst_ensemble_query",
+            "pst_status_str", "pst_last_error", "pst_supported_n", "pst_plan_create", "pst_plan_destroy",
             "pst_set_state", "pst_get_state", "pst_set_forcing", "pst_rhs", "pst_step", "pst_energy",
             "pst_spectrum", "pst_fft_r2c", "pst_fft_c2r", "pst_query", "pst_timer_read"]
 
@@ -239,3 +255,80 @@ def _np_dtype(x):
     import torch
     return {torch.complex64: np.complex64, torch.complex128: np.complex128,
             torch.float32: np.float32, torch.float64: np.float64}[x.dtype]
+
+
+ENS_MODES = {"graph": 0, "persistent": 1, "batched": 2, "sequential": 3}
+
+
+class Ensemble:
+    """Independent Navier-Stokes runs of uneven n (pst_ensemble_*), FP32."""
+
+    def __init__(self, sizes, rk_order=4, nu=1e-2, dt=1e-3, stream=None):
+        self.sizes = list(sizes)
+        p = pst_params(n=0, solver=PST_NS, precision=PST_FP32, rk_order=rk_order, nu=nu, eta=nu, dt=dt,
+                       dealias=0, flags=0)
+        arr = (ctypes.c_int * len(self.sizes))(*self.sizes)
+        h = _P()
+        s = lib.pst_ensemble_create(len(self.sizes), arr, ctypes.byref(p), _P(_stream_handle(stream)),
+                                    ctypes.byref(h))
+        if s != PST_OK:
+            raise PstError(s, lib.pst_ensemble_last_error(None).decode())
+        self._h = h
+
+    def _check(self, s):
+        if s != PST_OK:
+            raise PstError(s, lib.pst_ensemble_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pst_ensemble_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, run, uhat):
+        if isinstance(uhat, np.ndarray):
+            uhat = np.ascontiguousarray(uhat, np.complex64)
+        ptr, mem = _ptr(uhat)
+        self._check(lib.pst_ensemble_set_state(self._h, run, ptr, mem))
+
+    def get_state(self, run, out=None):
+        n = self.sizes[run]
+        if out is None:
+            out = np.empty((3, n, n, n // 2 + 1), np.complex64)
+        ptr, mem = _ptr(out)
+        self._check(lib.pst_ensemble_get_state(self._h, run, ptr, mem))
+        return out
+
+    def set_mode(self, mode):
+        self._check(lib.pst_ensemble_set_mode(self._h, ENS_MODES.get(mode, mode)))
+
+    def step(self, nsteps=1):
+        self._check(lib.pst_ensemble_step(self._h, nsteps))
+
+    def energy(self):
+        out = np.zeros(len(self.sizes), np.float64)
+        self._check(lib.pst_ensemble_energy(self._h, out.ctypes.data_as(_P)))
+        return out
+
+    def autotune(self, cache_path=None, force=False):
+        v = ctypes.c_int(-1)
+        self._check(lib.pst_ensemble_autotune(self._h, cache_path.encode() if cache_path else None, int(force),
+                                              ctypes.byref(v)))
+        return v.value
+
+    def set_schedule(self, variant):
+        self._check(lib.pst_ensemble_set_schedule(self._h, variant))
+
+    def query(self):
+        nc = ctypes.c_int()
+        cn = (ctypes.c_int * 4)()
+        cr = (ctypes.c_int * 4)()
+        var = ctypes.c_int()
+        grid = ctypes.c_int()
+        self._check(lib.pst_ensemble_query(self._h, ctypes.byref(nc), cn, cr, ctypes.byref(var), ctypes.byref(grid)))
+        return {"sizes": list(cn[:nc.value]), "runs": list(cr[:nc.value]), "variant": var.value, "grid": grid.value}

@@ -1,0 +1,127 @@
+"""GPU parity of ensembles of uneven-size runs: every run against the FP64
+oracle (relative L2 <= 1e-5 per field, FP32 path), in every execution mode
+and schedule variant; the modes agree bitwise; the autotuner picks and caches
+a variant."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1808_01309_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [32, 48, 32, 64, 96, 48]
+NU, DT, RK, NSTEPS = 1e-2, 1e-3, 4, 3
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1808_01309_amd import pst
+    return pst
+
+
+@pytest.fixture(scope="module")
+def init():
+    return [I.random_solenoidal(n, 100 + r) for r, n in enumerate(SIZES)]
+
+
+@pytest.fixture(scope="module")
+def ref(O, init):
+    return [O.step(u, NSTEPS, dt=DT, nu=NU, rk=RK) for u in init]
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def run_mode(P, init, mode, variant=None):
+    ens = P.Ensemble(SIZES, rk_order=RK, nu=NU, dt=DT)
+    if variant is not None:
+        ens.set_schedule(variant)
+    ens.set_mode(mode)
+    for r, u in enumerate(init):
+        ens.set_state(r, u)
+    ens.step(NSTEPS)
+    out = [ens.get_state(r) for r in range(len(SIZES))]
+    e = ens.energy()
+    ens.close()
+    return out, e
+
+
+@pytest.mark.parametrize("mode", ["graph", "persistent", "batched", "sequential"])
+def test_modes_match_oracle(O, P, init, ref, mode):
+    out, e = run_mode(P, init, mode)
+    for r in range(len(SIZES)):
+        for c in range(3):
+            assert rel(out[r][c], ref[r][c]) < 1e-5, (r, SIZES[r], c)
+        assert abs(e[r] - O.energy(ref[r])) < 1e-6 * O.energy(ref[r])
+
+
+def test_modes_bitwise_equal(P, init):
+    a, _ = run_mode(P, init, "graph")
+    b, _ = run_mode(P, init, "sequential")
+    c, _ = run_mode(P, init, "batched")
+    for r in range(len(SIZES)):
+        assert np.array_equal(a[r], b[r]) and np.array_equal(a[r], c[r])
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_variants_match_oracle(P, init, ref, variant):
+    out, _ = run_mode(P, init, "graph", variant)
+    for r in range(len(SIZES)):
+        assert rel(out[r], ref[r]) < 1e-5
+
+
+def test_graph_replay_many_steps(O, P):
+    """Replaying the captured step 20 times equals 20 directly launched steps."""
+    sizes = [48, 64]
+    init = [I.random_solenoidal(n, 7 + n) for n in sizes]
+    outs = []
+    for mode in ("graph", "persistent"):
+        ens = P.Ensemble(sizes, rk_order=4, nu=NU, dt=DT)
+        ens.set_mode(mode)
+        for r, u in enumerate(init):
+            ens.set_state(r, u)
+        ens.step(10)
+        ens.energy()          # host sync between replays
+        ens.step(10)
+        outs.append([ens.get_state(r) for r in range(2)])
+        ens.close()
+    for r in range(2):
+        assert np.array_equal(outs[0][r], outs[1][r])
+    ref = O.step(init[0], 20, dt=DT, nu=NU, rk=4)
+    assert rel(outs[0][0], ref) < 1e-5
+
+
+def test_autotune_and_cache(P, init, tmp_path):
+    path = str(tmp_path / "tune.json")
+    ens = P.Ensemble(SIZES, rk_order=RK, nu=NU, dt=DT)
+    for r, u in enumerate(init):
+        ens.set_state(r, u)
+    before = [ens.get_state(r) for r in range(len(SIZES))]
+    v = ens.autotune(path)
+    assert 0 <= v < 4
+    # the state survives the timing runs
+    for r in range(len(SIZES)):
+        assert np.array_equal(ens.get_state(r), before[r])
+    cache = json.load(open(path))
+    assert list(cache.values()) == [v]
+    assert ens.query()["variant"] == v
+    ens2 = P.Ensemble(SIZES, rk_order=RK, nu=NU, dt=DT)
+    assert ens2.autotune(path) == v        # served from the cache
+    assert ens2.query()["sizes"] == [32, 48, 64, 96]
+    assert ens2.query()["runs"] == [2, 2, 1, 1]
+
+
+def test_ensemble_errors(P):
+    with pytest.raises(P.PstError):
+        P.Ensemble([32, 40])
+    ens = P.Ensemble([32])
+    with pytest.raises(P.PstError):
+        ens.set_state(3, np.zeros((3, 32, 32, 17), np.complex64))
+    with pytest.raises(P.PstError):
+        ens.set_mode(9)
