@@ -107,35 +107,40 @@ __device__ __forceinline__ void zinv_body(const cx<T>* __restrict__ st, cx<T>* _
     const int64_t lin = (int64_t)kx * geo.M + jy;
     for (int grp = 0; grp < NGRP; ++grp) {
         const cx<T>* src = st + (int64_t)(grp * 3) * geo.sc + lin * geo.M;
-        // pass 1: the three components of v; pass 2: i k x v from the same
-        // (now cache-resident) line, so only 3 lines live in registers
-#pragma nounroll
-        for (int half = 0; half < 2; ++half) {
-            cx<T> u[3][E];
+        cx<T> u[3][E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = j_of_pos(F::first_pos(g, e), geo);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) u[c][e] = (active && j >= 0) ? src[c * geo.sc + j] : czero<T>();
+        }
+        // the curl components one at a time (i k x v)_c, then v itself: at
+        // most 4 lines live in registers and the state is read once
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<T> w[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const int j = j_of_pos(F::first_pos(g, e), geo);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) u[c][e] = (active && j >= 0) ? src[c * geo.sc + j] : czero<T>();
+                const T fkz = T(k_of_pos(F::first_pos(g, e), N));
+                const cx<T> a = u[0][e], b = u[1][e], d = u[2][e];
+                if (c == 0) w[e] = mul_i(cx<T>{fky * d.x - fkz * b.x, fky * d.y - fkz * b.y});
+                else if (c == 1) w[e] = mul_i(cx<T>{fkz * a.x - fkx * d.x, fkz * a.y - fkx * d.y});
+                else w[e] = mul_i(cx<T>{fkx * b.x - fky * a.x, fkx * b.y - fky * a.y});
             }
-            if (half == 1) {
+            F::run(w, g, lds, tw);
+            if (active) {
+                cx<T>* dst = A + (int64_t)(grp * 6 + 3 + c) * geo.sa + lin * N;
 #pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const T fkz = T(k_of_pos(F::first_pos(g, e), N));
-                    const cx<T> a = u[0][e], b = u[1][e], c = u[2][e];
-                    u[0][e] = mul_i(cx<T>{fky * c.x - fkz * b.x, fky * c.y - fkz * b.y});
-                    u[1][e] = mul_i(cx<T>{fkz * a.x - fkx * c.x, fkz * a.y - fkx * c.y});
-                    u[2][e] = mul_i(cx<T>{fkx * b.x - fky * a.x, fkx * b.y - fky * a.y});
-                }
+                for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = w[e];
             }
+        }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                F::run(u[c], g, lds, tw);
-                if (active) {
-                    cx<T>* dst = A + (int64_t)(grp * 6 + half * 3 + c) * geo.sa + lin * N;
+        for (int c = 0; c < 3; ++c) {
+            F::run(u[c], g, lds, tw);
+            if (active) {
+                cx<T>* dst = A + (int64_t)(grp * 6 + c) * geo.sa + lin * N;
 #pragma unroll
-                    for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = u[c][e];
-                }
+                for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = u[c][e];
             }
         }
     }
@@ -225,25 +230,35 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     const int64_t nn = (int64_t)N * N;
     const int64_t off = (int64_t)y * N + z;
     const int K = geo.K;
+    // Each kept row kx <= K of a pair (v, i k x v) is read from HBM once into
+    // LDS (coalesced along z); the packed line Z = V + i W and its Hermitian
+    // mirror Z(N - kx) = conj V + i conj W are then assembled from LDS.
     cx<T> v[NP][E];
+    cx<T>* const stage = sm + s * N * TLP;   // this tile's LDS (2 (K+1) TLP <= N TLP)
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int p = FI::first_pos(g, e);
-        const bool lo = p <= K, hi = p >= N - K;
-        const int kk = lo ? p : N - p;
+    for (int pi = 0; pi < NP; ++pi) {
+        const int fu = (pi / 3) * 6 + pi % 3, fw = fu + 3;
+        for (int kx = g; kx <= K; kx += G) {
+            stage[kx * TLP + t] = zin ? Bf[fu * geo.sb + kx * nn + off] : czero<T>();
+            stage[(K + 1 + kx) * TLP + t] = zin ? Bf[fw * geo.sb + kx * nn + off] : czero<T>();
+        }
+        __syncthreads();
 #pragma unroll
-        for (int pi = 0; pi < NP; ++pi) {
-            const int fu = (pi / 3) * 6 + pi % 3, fw = fu + 3;
+        for (int e = 0; e < E; ++e) {
+            const int p = FI::first_pos(g, e);
+            const bool lo = p <= K, hi = p >= N - K;
+            const int kk = lo ? p : N - p;
             cx<T> Z = czero<T>();
-            if (zin && (lo || hi)) {
-                const cx<T> U = Bf[fu * geo.sb + kk * nn + off];
-                const cx<T> W = Bf[fw * geo.sb + kk * nn + off];
+            if (lo || hi) {
+                const cx<T> U = stage[kk * TLP + t];
+                const cx<T> W = stage[(K + 1 + kk) * TLP + t];
                 if (p == 0) Z = {U.x, W.x};
                 else if (lo) Z = {U.x - W.y, U.y + W.x};
                 else Z = {U.x + W.y, W.x - U.y};
             }
             v[pi][e] = Z;
         }
+        __syncthreads();
     }
 #pragma unroll
     for (int pi = 0; pi < NP; ++pi) FI::run(v[pi], g, lds, tw);
