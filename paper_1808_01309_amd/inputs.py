@@ -217,3 +217,32 @@ def alfven_spec(n, k=1, amp=0.1, b0=1.0, dtype=np.complex128):
     b = -u.copy()
     b[2, 0, 0, 0] = b0
     return u, b
+
+
+# ------------------------------------------------------------ surrogate weights
+def fno_param_count(n, width, modes, layers, hidden):
+    """Length of the flat parameter vector of the Fourier neural operator:
+    lift W [width][3], b [width]; per layer Wc [width][width], bc [width],
+    R [(2 modes)^2 modes][width in][width out][re, im]; projection
+    Wq1 [hidden][width], bq1 [hidden], Wq2 [3][hidden], bq2 [3]."""
+    nm = (2 * modes) ** 2 * modes
+    return width * 3 + width + layers * (width * width + width + nm * width * width * 2) + \
+        hidden * width + hidden + 3 * hidden + 3
+
+
+def fno_init_params(n, width, modes, layers, hidden, seed=0, out_scale=0.01):
+    """Seeded initial parameters (numpy generator, float64), flat layout above:
+    dense weights N(0, 1/fan_in) (the last one times out_scale, so the
+    residual output starts close to the identity), biases 0, spectral weights
+    uniform in [0, 1) + i [0, 1) over width^2."""
+    rng = np.random.default_rng(seed)
+    nm = (2 * modes) ** 2 * modes
+    parts = [rng.standard_normal((width, 3)) / np.sqrt(3.0), np.zeros(width)]
+    for _ in range(layers):
+        parts += [rng.standard_normal((width, width)) / np.sqrt(width), np.zeros(width),
+                  rng.random((nm, width, width, 2)) / (width * width)]
+    parts += [rng.standard_normal((hidden, width)) / np.sqrt(width), np.zeros(hidden),
+              out_scale * rng.standard_normal((3, hidden)) / np.sqrt(hidden), np.zeros(3)]
+    theta = np.concatenate([p.reshape(-1) for p in parts])
+    assert theta.size == fno_param_count(n, width, modes, layers, hidden)
+    return theta
