@@ -223,6 +223,18 @@ pst_status pst_ensemble_set_mode(pst_ensemble *ens, int mode);
 /* Energy of every run (double[nruns]).  Synchronous. */
 pst_status pst_ensemble_energy(pst_ensemble *ens, double *per_run);
 
+/* Project every run's state onto divergence-free fields (k = 0 kept). */
+pst_status pst_ensemble_project(pst_ensemble *ens);
+
+/* Energy E = 1/2 sum w |uhat|^2 and enstrophy Z = 1/2 sum w |k|^2 |uhat|^2 of
+ * every run (double[nruns] each; dE/dt = -2 nu Z without forcing).  Synchronous. */
+pst_status pst_ensemble_diagnostics(pst_ensemble *ens, double *energy, double *enstrophy);
+
+/* Relative L2 distance ||a_r - b_r|| / ||b_r|| of every run between two
+ * ensembles with the same runs (double[nruns]).  Synchronous on a's stream
+ * (b's pending work must be complete). */
+pst_status pst_ensemble_rel_l2(pst_ensemble *a, const pst_ensemble *b, double *per_run);
+
 /* Pick the schedule variant (radix order x tile lines) by timing each on
  * persistent steps (the state is saved and restored around the timing).
  * cache_path (may be NULL) is a JSON object keyed by device architecture,
@@ -235,6 +247,58 @@ pst_status pst_ensemble_set_schedule(pst_ensemble *ens, int variant);
  * grid size.  Arrays need room for 4 entries; any pointer may be NULL. */
 pst_status pst_ensemble_query(const pst_ensemble *ens, int *nclasses, int *class_n, int *class_runs,
                               int *variant, int *grid);
+
+/* ------------------------------------------------------------------------
+ * Fourier-neural-operator surrogate that advances a velocity field by a
+ * fixed number of solver steps (not part of the paper's method; trained on
+ * the solver's own trajectories and judged by the solver):
+ *   v0 = Wl u + bl;  s_l = Wc_l v_l + bc_l + K_l(v_l);  v_{l+1} = gelu(s_l)
+ *   (identity after the last layer);  out = u + Wq2 gelu(Wq1 v_L + bq1) + bq2,
+ *   K_l(v) = c2r(R_l . r2c(v) on kx in [0, m), ky, kz in [0, m) U [n-m, n)).
+ * Dense channel mixing runs on the matrix cores (BF16 operands, FP32
+ * accumulation) unless mfma = 0 (FP32, for gradient checks); the spectral
+ * layers run this library's 3D transform kernels.
+ * Parameters are one float vector: Wl [w][3], bl [w], per layer Wc [w][w],
+ * bc [w], R [(2m)^2 m][w][w][re,im] (modes with kx fastest, then ky, kz each
+ * ordered [0, m) then [n-m, n)), then Wq1 [h][w], bq1 [h], Wq2 [3][h], bq2 [3].
+ * Fields are float, device, [batch][3][n][n][n] (z, y, x; x fastest).
+ * ---------------------------------------------------------------------- */
+typedef struct pst_fno pst_fno;
+
+typedef struct {
+    int n;       /* grid size (a supported n; n^3 a multiple of 32) */
+    int width;   /* channels w of the spectral layers (1..64) */
+    int modes;   /* m: retained modes per direction (2 m <= n) */
+    int layers;  /* spectral layers (1..8) */
+    int hidden;  /* h: projection hidden width (1..256) */
+    int batch;   /* maximum batch (1..64); buffers are sized for it */
+    int mfma;    /* 1: BF16 matrix-core channel mixing; 0: FP32 */
+} pst_fno_params;
+
+pst_status pst_fno_create(const pst_fno_params *p, void *hip_stream, pst_fno **out);
+void pst_fno_destroy(pst_fno *fno);
+const char *pst_fno_last_error(const pst_fno *fno);
+pst_status pst_fno_param_count(const pst_fno *fno, long long *count);
+
+/* Parameters / last gradient as float[count]; set_params also resets Adam. */
+pst_status pst_fno_set_params(pst_fno *fno, const float *theta, int mem);
+pst_status pst_fno_get_params(pst_fno *fno, float *theta, int mem);
+pst_status pst_fno_get_grad(pst_fno *fno, float *grad, int mem);
+
+/* out = surrogate(u) for batch <= p.batch samples (device buffers).  Stream-ordered. */
+pst_status pst_fno_forward(pst_fno *fno, const float *u, float *out, int batch);
+
+/* Forward, loss = mean_b ||out_b - tgt_b|| / ||tgt_b|| (written to *loss,
+ * double), and the gradient of the loss with respect to every parameter
+ * (kept in the object).  Synchronises the stream. */
+pst_status pst_fno_loss_grad(pst_fno *fno, const float *u, const float *tgt, int batch, double *loss);
+
+/* One Adam step from the stored gradient (FP32 master weights; the BF16
+ * copies used by the matrix cores are refreshed). */
+pst_status pst_fno_adam(pst_fno *fno, float lr, float beta1, float beta2, float eps);
+
+/* loss_grad followed by adam(lr, 0.9, 0.999, 1e-8). */
+pst_status pst_fno_train_step(pst_fno *fno, const float *u, const float *tgt, int batch, float lr, double *loss);
 
 #ifdef __cplusplus
 }

@@ -72,6 +72,95 @@ __global__ void k_ens_energy(EnsClass<T> c, double* out) {
     if (threadIdx.x == 0) out[run] = 0.5 * sh[0];
 }
 
+// energy and enstrophy of every run of a class (one block per run)
+template <typename T>
+__global__ void k_ens_diag(EnsClass<T> c, double* out_e, double* out_z) {
+    __shared__ double se[256], sz[256];
+    const int run = blockIdx.x;
+    const cx<T>* U = c.U + run * c.s_st;
+    const Geo& g = c.geo;
+    double ae = 0.0, az = 0.0;
+    for (int64_t i = threadIdx.x; i < g.sc; i += blockDim.x) {
+        const int jz = (int)(i % g.M), jy = (int)((i / g.M) % g.M), kx = (int)(i / ((int64_t)g.M * g.M));
+        const int ky = k_of_j(jy, g), kz = k_of_j(jz, g);
+        const double w = kx == 0 ? 1.0 : 2.0, k2 = (double)(kx * kx + ky * ky + kz * kz);
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const cx<T> v = U[k * g.sc + i];
+            s += (double)v.x * v.x + (double)v.y * v.y;
+        }
+        ae += w * s;
+        az += w * k2 * s;
+    }
+    se[threadIdx.x] = ae;
+    sz[threadIdx.x] = az;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            se[threadIdx.x] += se[threadIdx.x + w];
+            sz[threadIdx.x] += sz[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out_e[run] = 0.5 * se[0];
+        out_z[run] = 0.5 * sz[0];
+    }
+}
+
+// projection onto divergence-free fields of every run of a class (k = 0 kept)
+template <typename T>
+__global__ void k_ens_project(EnsClass<T> c) {
+    const Geo& g = c.geo;
+    const int64_t total = (int64_t)c.nruns * g.sc;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int run = (int)(t / g.sc);
+        const int64_t i = t % g.sc;
+        const int jz = (int)(i % g.M), jy = (int)((i / g.M) % g.M), kx = (int)(i / ((int64_t)g.M * g.M));
+        const T fx = T(kx), fy = T(k_of_j(jy, g)), fz = T(k_of_j(jz, g));
+        const T k2 = fx * fx + fy * fy + fz * fz;
+        if (k2 == T(0)) continue;
+        cx<T>* U = c.U + run * c.s_st + i;
+        const cx<T> a = U[0], b = U[g.sc], d = U[2 * g.sc];
+        const cx<T> kv = {(fx * a.x + fy * b.x + fz * d.x) / k2, (fx * a.y + fy * b.y + fz * d.y) / k2};
+        U[0] = {a.x - fx * kv.x, a.y - fx * kv.y};
+        U[g.sc] = {b.x - fy * kv.x, b.y - fy * kv.y};
+        U[2 * g.sc] = {d.x - fz * kv.x, d.y - fz * kv.y};
+    }
+}
+
+// per run: sum w |a - b|^2 and sum w |b|^2 (one block per run)
+template <typename T>
+__global__ void k_ens_dist(EnsClass<T> a, EnsClass<T> b, double* out) {
+    __shared__ double sd[256], sb[256];
+    const int run = blockIdx.x;
+    const Geo& g = a.geo;
+    const cx<T>* A = a.U + run * a.s_st;
+    const cx<T>* Bv = b.U + run * b.s_st;
+    double dd = 0.0, bb = 0.0;
+    for (int64_t i = threadIdx.x; i < 3 * g.sc; i += blockDim.x) {
+        const double w = ((i % g.sc) / ((int64_t)g.M * g.M)) == 0 ? 1.0 : 2.0;
+        const cx<T> x = A[i], y = Bv[i];
+        const double ex = (double)x.x - y.x, ey = (double)x.y - y.y;
+        dd += w * (ex * ex + ey * ey);
+        bb += w * ((double)y.x * y.x + (double)y.y * y.y);
+    }
+    sd[threadIdx.x] = dd;
+    sb[threadIdx.x] = bb;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sd[threadIdx.x] += sd[threadIdx.x + w];
+            sb[threadIdx.x] += sb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * run] = sd[0];
+        out[2 * run + 1] = sb[0];
+    }
+}
+
 template <typename T>
 __global__ void k_ens_gather(const cx<T>* __restrict__ abi, cx<T>* __restrict__ st, Geo g) {
     const int64_t total = 3 * g.sc;
@@ -343,7 +432,7 @@ extern "C" pst_status pst_ensemble_create(int nruns, const int* n, const pst_par
         maxspec = std::max(maxspec, (size_t)3 * h.n * h.n * (h.n / 2 + 1) * es);
         if (!ok) break;
     }
-    ok = ok && alloc((void**)&E->bar, 64) && alloc((void**)&E->err, 64) && alloc((void**)&E->eout, sizeof(double) * nruns) &&
+    ok = ok && alloc((void**)&E->bar, 64) && alloc((void**)&E->err, 64) && alloc((void**)&E->eout, sizeof(double) * 2 * nruns) &&
          alloc(&E->scratch, maxspec);
     E->scratch_bytes = maxspec;
     if (!ok) {
@@ -608,5 +697,60 @@ extern "C" pst_status pst_ensemble_query(const pst_ensemble* E, int* nclasses, i
     }
     if (variant) *variant = E->var;
     if (grid) *grid = E->grids[E->var];
+    return PST_OK;
+}
+
+extern "C" pst_status pst_ensemble_project(pst_ensemble* E) {
+    if (!E) return PST_ERR_INVALID_ARG;
+    EnsDesc<float> d = make_desc(E);
+    for (int c = 0; c < d.ncls; ++c)
+        hipLaunchKernelGGL(k_ens_project<float>, dim3(512), dim3(256), 0, E->stream, d.cls[c]);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PST_OK : efail(E, PST_ERR_HIP, "projection launch failed");
+}
+
+extern "C" pst_status pst_ensemble_diagnostics(pst_ensemble* E, double* energy, double* enstrophy) {
+    if (!E) return PST_ERR_INVALID_ARG;
+    if (!energy || !enstrophy) return efail(E, PST_ERR_INVALID_ARG, "NULL output");
+    EnsDesc<float> d = make_desc(E);
+    for (int c = 0; c < d.ncls; ++c) {
+        const EnsClassHost& h = E->cls[c];
+        const size_t R = h.runs.size();
+        hipLaunchKernelGGL(k_ens_diag<float>, dim3((unsigned)R), dim3(256), 0, E->stream, d.cls[c], E->eout,
+                           E->eout + R);
+        std::vector<double> part(2 * R);
+        if (hipMemcpyAsync(part.data(), E->eout, sizeof(double) * 2 * R, hipMemcpyDeviceToHost, E->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(E->stream) != hipSuccess)
+            return efail(E, PST_ERR_HIP, "diagnostics readback failed");
+        for (size_t i = 0; i < R; ++i) {
+            energy[h.runs[i]] = part[i];
+            enstrophy[h.runs[i]] = part[R + i];
+        }
+    }
+    for (int r = 0; r < E->nruns; ++r)
+        if (!isfinite(energy[r]) || !isfinite(enstrophy[r])) return efail(E, PST_ERR_NONFINITE, "run %d diagnostics", r);
+    return PST_OK;
+}
+
+extern "C" pst_status pst_ensemble_rel_l2(pst_ensemble* A, const pst_ensemble* Bn, double* per_run) {
+    if (!A || !Bn) return PST_ERR_INVALID_ARG;
+    if (!per_run) return efail(A, PST_ERR_INVALID_ARG, "NULL output");
+    if (A->nruns != Bn->nruns || A->cls.size() != Bn->cls.size()) return efail(A, PST_ERR_INVALID_ARG, "ensembles differ");
+    for (size_t c = 0; c < A->cls.size(); ++c)
+        if (A->cls[c].n != Bn->cls[c].n || A->cls[c].runs != Bn->cls[c].runs)
+            return efail(A, PST_ERR_INVALID_ARG, "ensembles differ");
+    EnsDesc<float> da = make_desc(A), db = make_desc(const_cast<pst_ensemble*>(Bn));
+    for (int c = 0; c < da.ncls; ++c) {
+        const EnsClassHost& h = A->cls[c];
+        const size_t R = h.runs.size();
+        hipLaunchKernelGGL(k_ens_dist<float>, dim3((unsigned)R), dim3(256), 0, A->stream, da.cls[c], db.cls[c], A->eout);
+        std::vector<double> part(2 * R);
+        if (hipMemcpyAsync(part.data(), A->eout, sizeof(double) * 2 * R, hipMemcpyDeviceToHost, A->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(A->stream) != hipSuccess)
+            return efail(A, PST_ERR_HIP, "readback failed");
+        for (size_t i = 0; i < R; ++i) per_run[h.runs[i]] = sqrt(part[2 * i] / part[2 * i + 1]);
+    }
     return PST_OK;
 }

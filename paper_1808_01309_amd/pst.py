@@ -76,7 +76,9 @@ _ens_sigs = [("pst_ensemble_create", [_I, _P, ctypes.POINTER(pst_params), _P, ct
              ("pst_ensemble_set_state", [_P, _I, _P, _I]), ("pst_ensemble_get_state", [_P, _I, _P, _I]),
              ("pst_ensemble_step", [_P, _I]), ("pst_ensemble_set_mode", [_P, _I]),
              ("pst_ensemble_energy", [_P, _P]), ("pst_ensemble_autotune", [_P, ctypes.c_char_p, _I, _P]),
-             ("pst_ensemble_set_schedule", [_P, _I]), ("pst_ensemble_query", [_P, _P, _P, _P, _P, _P])]
+             ("pst_ensemble_set_schedule", [_P, _I]), ("pst_ensemble_query", [_P, _P, _P, _P, _P, _P]),
+             ("pst_ensemble_project", [_P]), ("pst_ensemble_diagnostics", [_P, _P, _P]),
+             ("pst_ensemble_rel_l2", [_P, _P, _P])]
 for _name, _args in _ens_sigs:
     getattr(lib, _name).argtypes = _args
     getattr(lib, _name).restype = _S
@@ -85,9 +87,32 @@ lib.pst_ensemble_destroy.restype = None
 lib.pst_ensemble_last_error.argtypes = [_P]
 lib.pst_ensemble_last_error.restype = ctypes.c_char_p
 
-EXPORTED = ["pst_ensemble_create", "pst_ensemble_destroy", "pst_ensemble_last_error", "pst_ensemble_set_state",
+class pst_fno_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("width", ctypes.c_int), ("modes", ctypes.c_int), ("layers", ctypes.c_int),
+                ("hidden", ctypes.c_int), ("batch", ctypes.c_int), ("mfma", ctypes.c_int)]
+
+
+for _name, _args in [("pst_fno_create", [ctypes.POINTER(pst_fno_params), _P, ctypes.POINTER(_P)]),
+                     ("pst_fno_param_count", [_P, ctypes.POINTER(ctypes.c_longlong)]),
+                     ("pst_fno_set_params", [_P, _P, _I]), ("pst_fno_get_params", [_P, _P, _I]),
+                     ("pst_fno_get_grad", [_P, _P, _I]), ("pst_fno_forward", [_P, _P, _P, _I]),
+                     ("pst_fno_loss_grad", [_P, _P, _P, _I, ctypes.POINTER(ctypes.c_double)]),
+                     ("pst_fno_adam", [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+                     ("pst_fno_train_step", [_P, _P, _P, _I, ctypes.c_float, ctypes.POINTER(ctypes.c_double)])]:
+    getattr(lib, _name).argtypes = _args
+    getattr(lib, _name).restype = _S
+lib.pst_fno_destroy.argtypes = [_P]
+lib.pst_fno_destroy.restype = None
+lib.pst_fno_last_error.argtypes = [_P]
+lib.pst_fno_last_error.restype = ctypes.c_char_p
+
+EXPORTED = ["pst_fno_create", "pst_fno_destroy", "pst_fno_last_error", "pst_fno_param_count", "pst_fno_set_params",
+            "pst_fno_get_params", "pst_fno_get_grad", "pst_fno_forward", "pst_fno_loss_grad", "pst_fno_adam",
+            "pst_fno_train_step",
+            "pst_ensemble_create", "pst_ensemble_destroy", "pst_ensemble_last_error", "pst_ensemble_set_state",
             "pst_ensemble_get_state", "pst_ensemble_step", "pst_ensemble_set_mode", "pst_ensemble_energy",
-            "pst_ensemble_autotune", "pst_ensemble_set_schedule", "pst_ensemble_query",
+            "pst_ensemble_autotune", "pst_ensemble_set_schedule", "pst_ensemble_query", "pst_ensemble_project",
+            "pst_ensemble_diagnostics", "pst_ensemble_rel_l2",
             "pst_status_str", "pst_last_error", "pst_supported_n", "pst_plan_create", "pst_plan_destroy",
             "pst_set_state", "pst_get_state", "pst_set_forcing", "pst_rhs", "pst_step", "pst_energy",
             "pst_spectrum", "pst_fft_r2c", "pst_fft_c2r", "pst_query", "pst_timer_read"]
@@ -315,6 +340,20 @@ class Ensemble:
         self._check(lib.pst_ensemble_energy(self._h, out.ctypes.data_as(_P)))
         return out
 
+    def project(self):
+        self._check(lib.pst_ensemble_project(self._h))
+
+    def diagnostics(self):
+        e = np.zeros(len(self.sizes), np.float64)
+        z = np.zeros(len(self.sizes), np.float64)
+        self._check(lib.pst_ensemble_diagnostics(self._h, e.ctypes.data_as(_P), z.ctypes.data_as(_P)))
+        return e, z
+
+    def rel_l2(self, other):
+        out = np.zeros(len(self.sizes), np.float64)
+        self._check(lib.pst_ensemble_rel_l2(self._h, other._h, out.ctypes.data_as(_P)))
+        return out
+
     def autotune(self, cache_path=None, force=False):
         v = ctypes.c_int(-1)
         self._check(lib.pst_ensemble_autotune(self._h, cache_path.encode() if cache_path else None, int(force),
@@ -332,3 +371,66 @@ class Ensemble:
         grid = ctypes.c_int()
         self._check(lib.pst_ensemble_query(self._h, ctypes.byref(nc), cn, cr, ctypes.byref(var), ctypes.byref(grid)))
         return {"sizes": list(cn[:nc.value]), "runs": list(cr[:nc.value]), "variant": var.value, "grid": grid.value}
+
+
+class FNO:
+    """Fourier-neural-operator surrogate (pst_fno_*); tensors are torch CUDA float32."""
+
+    def __init__(self, n, width=32, modes=12, layers=4, hidden=128, batch=8, mfma=True, stream=None):
+        self.cfg = dict(n=n, width=width, modes=modes, layers=layers, hidden=hidden)
+        self.batch = batch
+        p = pst_fno_params(n=n, width=width, modes=modes, layers=layers, hidden=hidden, batch=batch, mfma=int(mfma))
+        h = _P()
+        s = lib.pst_fno_create(ctypes.byref(p), _P(_stream_handle(stream)), ctypes.byref(h))
+        if s != PST_OK:
+            raise PstError(s, lib.pst_fno_last_error(None).decode())
+        self._h = h
+        c = ctypes.c_longlong()
+        self._check(lib.pst_fno_param_count(h, ctypes.byref(c)))
+        self.nparam = c.value
+
+    def _check(self, s):
+        if s != PST_OK:
+            raise PstError(s, lib.pst_fno_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.pst_fno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, np.float32)
+        assert theta.size == self.nparam
+        self._check(lib.pst_fno_set_params(self._h, theta.ctypes.data_as(_P), PST_MEM_HOST))
+
+    def get_params(self):
+        out = np.empty(self.nparam, np.float32)
+        self._check(lib.pst_fno_get_params(self._h, out.ctypes.data_as(_P), PST_MEM_HOST))
+        return out
+
+    def get_grad(self):
+        out = np.empty(self.nparam, np.float32)
+        self._check(lib.pst_fno_get_grad(self._h, out.ctypes.data_as(_P), PST_MEM_HOST))
+        return out
+
+    def forward(self, u, out):
+        self._check(lib.pst_fno_forward(self._h, _ptr(u)[0], _ptr(out)[0], u.shape[0]))
+
+    def loss_grad(self, u, tgt):
+        L = ctypes.c_double()
+        self._check(lib.pst_fno_loss_grad(self._h, _ptr(u)[0], _ptr(tgt)[0], u.shape[0], ctypes.byref(L)))
+        return L.value
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(lib.pst_fno_adam(self._h, lr, beta1, beta2, eps))
+
+    def train_step(self, u, tgt, lr):
+        L = ctypes.c_double()
+        self._check(lib.pst_fno_train_step(self._h, _ptr(u)[0], _ptr(tgt)[0], u.shape[0], lr, ctypes.byref(L)))
+        return L.value

@@ -125,3 +125,40 @@ def test_ensemble_errors(P):
         ens.set_state(3, np.zeros((3, 32, 32, 17), np.complex64))
     with pytest.raises(P.PstError):
         ens.set_mode(9)
+
+
+def test_project_diagnostics_distance(O, P):
+    sizes = [32, 48]
+    rng = np.random.default_rng(9)
+    ens = P.Ensemble(sizes)
+    raw = []
+    for r, n in enumerate(sizes):
+        # a real but non-solenoidal field: random physical data, dealiased
+        ur = rng.standard_normal((3, n, n, n))
+        uh = O.r2c_vec(ur) * I.cube_mask(n)[None]
+        raw.append(uh)
+        ens.set_state(r, uh)
+    ens.project()
+    e, z = ens.diagnostics()
+    for r, n in enumerate(sizes):
+        got = ens.get_state(r).astype(np.complex128)
+        kx, ky, kz = [np.broadcast_to(k, (n, n, n // 2 + 1)).astype(float) for k in I.wavenumbers(n)]
+        k2 = kx ** 2 + ky ** 2 + kz ** 2
+        k2[0, 0, 0] = 1.0
+        kd = (kx * raw[r][0] + ky * raw[r][1] + kz * raw[r][2]) / k2
+        ref = raw[r] - np.stack([kx * kd, ky * kd, kz * kd])
+        assert np.abs(got - ref).max() < 1e-6 * np.abs(ref).max()
+        assert abs(e[r] - O.energy(got)) < 1e-12 * e[r]
+        # enstrophy = energy of the vorticity i k x u (u solenoidal)
+        w = 1j * np.stack([ky * got[2] - kz * got[1], kz * got[0] - kx * got[2], kx * got[1] - ky * got[0]])
+        assert abs(z[r] - O.energy(w)) < 1e-10 * z[r]
+    other = P.Ensemble(sizes)
+    states = []
+    for r, n in enumerate(sizes):
+        b = I.random_solenoidal(n, 40 + r)
+        states.append(b.astype(np.complex64).astype(np.complex128))
+        other.set_state(r, b)
+    d = ens.rel_l2(other)
+    for r in range(len(sizes)):
+        a = ens.get_state(r).astype(np.complex128)
+        assert abs(d[r] - np.sqrt(O.energy(a - states[r]) / O.energy(states[r]))) < 1e-6

@@ -1,0 +1,55 @@
+"""End-to-end surrogate pipeline on a small grid: solver-generated pairs,
+training lowers the loss, and the hybrid rollout's guard hands every window
+to the solver when the surrogate is broken (the result then tracks the plain
+solver rollout)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+N = 32
+CFG = dict(n=N, width=8, modes=4, layers=2, hidden=16)
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1808_01309_amd import surrogate
+    return surrogate
+
+
+@pytest.fixture(scope="module")
+def data(S):
+    return S.generate(4, n=N, steps=30, seed0=1000)
+
+
+def test_generated_pairs_match_solver(S, data, O):
+    """The stored trajectory equals the oracle's trajectory (FP32 tolerance)."""
+    from paper_1808_01309_amd import inputs as I
+    u0 = I.random_solenoidal(N, 1000, dtype=np.complex64).astype(np.complex128)
+    ref = O.c2r_vec(O.step(u0, 30, dt=1e-3, nu=1e-2, rk=4))
+    got = data[0, 30].cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5
+
+
+def test_training_lowers_loss(S, data):
+    from paper_1808_01309_amd import inputs as I
+    from paper_1808_01309_amd import pst
+    fno = pst.FNO(batch=4, mfma=True, **CFG)
+    fno.set_params(I.fno_init_params(seed=0, **CFG))
+    hist = S.train(fno, data, iters=60, batch=4, lr=3e-3, horizon=10)
+    assert hist[-10:].mean() < 0.7 * hist[:5].mean()
+
+
+def test_guard_hands_broken_surrogate_to_solver(S, data):
+    import torch
+    from paper_1808_01309_amd import inputs as I
+    from paper_1808_01309_amd import pst
+    fno = pst.FNO(batch=2, mfma=True, **CFG)
+    fno.set_params(I.fno_init_params(seed=1, out_scale=50.0, **CFG))   # garbage output
+    x0 = data[2:4, 0].contiguous()
+    st = S.rollout(fno, x0, apps=6, horizon=3, audit_every=3)
+    assert st["guard_fail"] >= 3 and st["solver_windows"] >= 2
+    assert max(st["final_rel_l2"]) < 1e-4
+    assert st["t_hybrid_s"] > 0 and st["t_plain_s"] > 0
