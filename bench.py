@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fft", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counter scaling)")
     return ap.parse_args()
@@ -110,6 +111,44 @@ def run_fft(pst, torch, n, prec, reps=5, nf=3):
     plan.close()
     del x, y, z
     torch.cuda.empty_cache()
+    return res
+
+
+def run_ensemble(pst, torch, I, steps=200, seq_steps=10):
+    """96 Navier-Stokes runs of uneven size (32 x 48^3, 48 x 64^3, 16 x 96^3), FP32,
+    RK4, dt = 1e-3, nu = 1e-2, random-phase initial fields (seeds 0..95):
+    `steps` steps with the persistent kernel replayed from a HIP graph, and a
+    shorter timing of the batched and the per-run sequential launches of the
+    same kernels."""
+    sizes = [48] * 32 + [64] * 48 + [96] * 16
+    ens = pst.Ensemble(sizes, rk_order=4, nu=1e-2, dt=1e-3)
+    init = [I.random_solenoidal(n, r, dtype=np.complex64) for r, n in enumerate(sizes)]
+    for r, u in enumerate(init):
+        ens.set_state(r, u)
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "pst_ensemble_autotune.json")
+    variant = ens.autotune(cache)
+    res = {"runs": len(sizes), "sizes": {"48": 32, "64": 48, "96": 16}, "variant": variant,
+           "grid_blocks": ens.query()["grid"]}
+    timings = {}
+    for mode, nst in (("graph", steps), ("persistent", seq_steps), ("batched", seq_steps), ("sequential", seq_steps)):
+        for r, u in enumerate(init):
+            ens.set_state(r, u)
+        ens.set_mode(mode)
+        ens.step(1)                      # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ens.step(nst)
+        torch.cuda.synchronize()
+        timings[mode] = (time.perf_counter() - t0) * 1e3 / nst
+    pts = sum(n ** 3 for n in sizes)
+    res["ms_per_step"] = timings
+    res["wall_s_200_steps_graph"] = timings["graph"] * steps / 1e3
+    res["point_steps_per_s"] = pts / (timings["graph"] / 1e3)
+    res["speedup_vs_sequential"] = timings["sequential"] / timings["graph"]
+    res["speedup_vs_batched"] = timings["batched"] / timings["graph"]
+    e = ens.energy()
+    res["energy_range_end"] = [float(e.min()), float(e.max())]
+    ens.close()
     return res
 
 
@@ -196,6 +235,9 @@ def main():
             fb = fft_bytes(n, 3, esz)
             ffts[prec] = {d: {k: {"ms": r[d][k], "GB_s": fb[k] / r[d][k] / 1e6} for k in fb} for d in r}
         out_extra["fft_3fields"] = ffts
+    if not a.no_ensemble:
+        print("[bench] ensemble: 96 runs (48^3, 64^3, 96^3), 200 RK4 steps", file=sys.stderr, flush=True)
+        out_extra["ensemble"] = run_ensemble(pst, torch, I)
     # dominant kernel of the headline (FP32) step
     dom = max(KINDS, key=lambda k: tm32[k][0])
     ach = kb32[dom] / per32[dom] / 1e6

@@ -24,19 +24,20 @@ from . import pst
 
 
 class Converter:
-    """Spectral (library layout) <-> physical fields with the library's FFTs."""
+    """Spectral (library layout) <-> physical fields with the library's FFTs,
+    for batches of `batch` 3-component fields in one transform call."""
 
-    def __init__(self, n):
+    def __init__(self, n, batch=1):
         import torch
         self.n = n
         self.plan = pst.Plan(n, precision="fp32")
-        self.spec = torch.empty((3, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+        self.spec = torch.empty((batch, 3, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
 
-    def to_phys(self, spec, out):
-        self.plan.fft_c2r(spec, out, 3)
+    def to_phys(self, spec, out, nfields=3):
+        self.plan.fft_c2r(spec, out, nfields)
 
-    def to_spec(self, phys, out):
-        self.plan.fft_r2c(phys, out, 3)
+    def to_spec(self, phys, out, nfields=3):
+        self.plan.fft_r2c(phys, out, nfields)
 
 
 def generate(nseeds, n=64, steps=510, seed0=1000, nu=1e-2, dt=1e-3, rk=4, spectrum=I.spectrum_c2, log=None):
@@ -50,8 +51,8 @@ def generate(nseeds, n=64, steps=510, seed0=1000, nu=1e-2, dt=1e-3, rk=4, spectr
 
     def grab(t):
         for s in range(nseeds):
-            ens.get_state(s, conv.spec)
-            conv.to_phys(conv.spec, data[s, t])
+            ens.get_state(s, conv.spec[0])
+            conv.to_phys(conv.spec[0], data[s, t])
 
     grab(0)
     for t in range(1, steps + 1):
@@ -87,7 +88,8 @@ def train(fno, data, iters=2000, batch=8, lr=1e-3, decay_every=500, gamma=0.5, h
 
 
 class _Stage:
-    """An ensemble plus the buffers to move its states to and from physical space."""
+    """An ensemble plus the buffers to move its states to and from physical space
+    (one transform call for all runs)."""
 
     def __init__(self, sizes, nu, dt, rk, conv):
         self.ens = pst.Ensemble(sizes, rk_order=rk, nu=nu, dt=dt)
@@ -95,16 +97,16 @@ class _Stage:
         self.nb = len(sizes)
 
     def load(self, phys, project=False):
+        self.conv.to_spec(phys, self.conv.spec, 3 * self.nb)
         for b in range(self.nb):
-            self.conv.to_spec(phys[b], self.conv.spec)
-            self.ens.set_state(b, self.conv.spec)
+            self.ens.set_state(b, self.conv.spec[b])
         if project:
             self.ens.project()
 
     def store(self, phys):
         for b in range(self.nb):
-            self.ens.get_state(b, self.conv.spec)
-            self.conv.to_phys(self.conv.spec, phys[b])
+            self.ens.get_state(b, self.conv.spec[b])
+        self.conv.to_phys(self.conv.spec, phys, 3 * self.nb)
 
 
 def rollout(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4, tol=1e-2, tau_e=2e-3,
@@ -122,7 +124,7 @@ def rollout(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4, tol=1e-
     true error of every window (outside the hybrid timing)."""
     import torch
     B, n = init_phys.shape[0], init_phys.shape[-1]
-    conv = Converter(n)
+    conv = Converter(n, B)
     sizes = [n] * B
     sur = _Stage(sizes, nu, dt, rk, conv)     # holds the surrogate's (projected) state
     sol = _Stage(sizes, nu, dt, rk, conv)     # solver windows and audits
@@ -201,7 +203,7 @@ def window_errors(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4):
     against the plain solver at every window."""
     import torch
     B, n = init_phys.shape[0], init_phys.shape[-1]
-    conv = Converter(n)
+    conv = Converter(n, B)
     sizes = [n] * B
     ref = _Stage(sizes, nu, dt, rk, conv)
     sur = _Stage(sizes, nu, dt, rk, conv)

@@ -83,7 +83,7 @@ def test_adam_reduces_loss(P, torch, case, mfma):
     ud = torch.from_numpy(u).float().cuda()
     td = torch.from_numpy(tgt).float().cuda()
     losses = [fno.train_step(ud, td, 1e-3) for _ in range(8)]
-    assert losses[-1] < 0.8 * losses[0]
+    assert losses[-1] < 0.9 * losses[0] and all(np.diff(losses) < 0.02 * losses[0])
 
 
 def test_adam_matches_formula(P, torch, case):
