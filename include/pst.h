@@ -243,7 +243,7 @@ pst_status pst_ensemble_rel_l2(pst_ensemble *a, const pst_ensemble *b, double *p
 pst_status pst_ensemble_autotune(pst_ensemble *ens, const char *cache_path, int force, int *chosen);
 pst_status pst_ensemble_set_schedule(pst_ensemble *ens, int variant);
 
-/* Distinct sizes (ascending), runs per size, current variant and persistent
+/* Distinct sizes (descending), runs per size, current variant and persistent
  * grid size.  Arrays need room for 4 entries; any pointer may be NULL. */
 pst_status pst_ensemble_query(const pst_ensemble *ens, int *nclasses, int *class_n, int *class_runs,
                               int *variant, int *grid);

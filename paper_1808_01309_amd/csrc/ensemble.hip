@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <fstream>
+#include <functional>
 #include <map>
 #include <sstream>
 #include <string>
@@ -223,6 +224,8 @@ struct pst_ensemble {
     int mode;
     int var;
     int grids[ENS_NVAR];
+    EnsDesc<float> desc_host;     // last descriptor uploaded to desc_dev
+    EnsDesc<float>* desc_dev;
     unsigned* bar;
     int* err;
     double* eout;
@@ -302,8 +305,13 @@ static void launch_step(pst_ensemble* E) {
     EnsDesc<float> d = make_desc(E);
     const EnsKernels* K = ens_kernels(E->var);
     if (E->mode == 0 || E->mode == 1) {
+        // the descriptor only changes with the schedule: upload it when it does
+        if (memcmp(&d, &E->desc_host, sizeof d) != 0) {
+            E->desc_host = d;
+            hipMemcpyAsync(E->desc_dev, &E->desc_host, sizeof d, hipMemcpyHostToDevice, E->stream);
+        }
         hipLaunchKernelGGL(k_ens_reset, dim3(1), dim3(64), 0, E->stream, E->bar, E->err);
-        K->launch_persistent(d, E->grids[E->var], E->stream);
+        K->launch_persistent(E->desc_dev, E->grids[E->var], E->stream);
         return;
     }
     for (int s = 0; s < d.nstages; ++s)
@@ -354,7 +362,7 @@ extern "C" void pst_ensemble_destroy(pst_ensemble* E) {
     for (auto& c : E->cls)
         for (void* p : {c.U, c.V, c.Acc, c.A, c.B, c.C, c.tw, c.E, c.E2})
             if (p) hipFree(p);
-    for (void* p : {(void*)E->bar, (void*)E->err, (void*)E->eout, E->scratch})
+    for (void* p : {(void*)E->desc_dev, (void*)E->bar, (void*)E->err, (void*)E->eout, E->scratch})
         if (p) hipFree(p);
     delete E;
 }
@@ -375,7 +383,9 @@ extern "C" pst_status pst_ensemble_create(int nruns, const int* n, const pst_par
     if (!(common->dt > 0.0) || !(common->nu >= 0.0) || !isfinite(common->dt) || !isfinite(common->nu))
         return efail(nullptr, PST_ERR_INVALID_ARG, "dt must be > 0 and nu >= 0");
     if (common->flags != 0) return efail(nullptr, PST_ERR_UNSUPPORTED, "flags are not supported for ensembles");
-    std::map<int, int> cls_of;
+    // classes in descending n: the persistent kernel hands out the most
+    // expensive work units first
+    std::map<int, int, std::greater<int>> cls_of;
     for (int r = 0; r < nruns; ++r) {
         if (!ens_supported_n(n[r])) return efail(nullptr, PST_ERR_UNSUPPORTED_N, "run %d: n = %d", r, n[r]);
         if (!cls_of.count(n[r])) cls_of[n[r]] = 0;
@@ -387,6 +397,7 @@ extern "C" pst_status pst_ensemble_create(int nruns, const int* n, const pst_par
     E->nruns = nruns;
     E->mode = 0;
     E->graph_valid = false;
+    memset(&E->desc_host, 0xff, sizeof E->desc_host);
     int ci = 0;
     for (auto& kv : cls_of) {
         kv.second = ci++;
@@ -432,7 +443,7 @@ extern "C" pst_status pst_ensemble_create(int nruns, const int* n, const pst_par
         maxspec = std::max(maxspec, (size_t)3 * h.n * h.n * (h.n / 2 + 1) * es);
         if (!ok) break;
     }
-    ok = ok && alloc((void**)&E->bar, 64) && alloc((void**)&E->err, 64) && alloc((void**)&E->eout, sizeof(double) * 2 * nruns) &&
+    ok = ok && alloc((void**)&E->desc_dev, sizeof(EnsDesc<float>)) && alloc((void**)&E->bar, 64) && alloc((void**)&E->err, 64) && alloc((void**)&E->eout, sizeof(double) * 2 * nruns) &&
          alloc(&E->scratch, maxspec);
     E->scratch_bytes = maxspec;
     if (!ok) {

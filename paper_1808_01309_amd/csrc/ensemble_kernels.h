@@ -94,7 +94,7 @@ inline void ens_units(const Geo& g, int64_t* upr) {
 
 // One work unit of one pass of one run.
 template <typename T, int N, int V>
-__device__ __noinline__ void ens_unit_v(const EnsClass<T>& c, int pass, int stage_in_v, int mode, T h, int run,
+__device__ __forceinline__ void ens_unit_v(const EnsClass<T>& c, int pass, int stage_in_v, int mode, T h, int run,
                                            int64_t lu, cx<T>* sm) {
     using TC = EnsCfg<T, N, V>;
     using LC = EnsLineCfg<T, N, V>;
@@ -174,23 +174,35 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, int* err, unsigned n
     return ok_sh != 0;
 }
 
+// The units of one pass of one class, handed out round-robin over the grid;
+// `first` is the global index of the class's first unit (units of all
+// classes of a pass form one sequence, largest grids first).
+template <typename T, int N, int V>
+__device__ __forceinline__ void ens_class_pass(const EnsClass<T>& c, int pass, int sv, int mode, T h, int64_t first,
+                                               cx<T>* sm) {
+    const int64_t upr = c.upr[pass], total = c.nruns * upr;
+    int64_t u = ((int64_t)blockIdx.x - first) % gridDim.x;
+    if (u < 0) u += gridDim.x;
+    for (; u < total; u += gridDim.x) ens_unit_v<T, N, V>(c, pass, sv, mode, h, (int)(u / upr), u % upr, sm);
+}
+
 template <typename T, int V>
-__global__ __launch_bounds__(ENS_NT) void k_ens_persistent(EnsDesc<T> d) {
+__global__ __launch_bounds__(ENS_NT, 2) void k_ens_persistent(const EnsDesc<T>* __restrict__ dp) {
     __shared__ cx<T> sm[ens_lds<T>()];
+    const EnsDesc<T>& d = *dp;   // device-resident descriptor
     if (__hip_atomic_load(d.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     for (int s = 0; s < d.nstages; ++s) {
         for (int pass = 0; pass < 5; ++pass) {
-            int64_t total = 0;
-            for (int c = 0; c < d.ncls; ++c) total += d.cls[c].nruns * d.cls[c].upr[pass];
-            for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
-                int64_t r = u;
-                int c = 0;
-                while (c + 1 < d.ncls && r >= d.cls[c].nruns * d.cls[c].upr[pass]) {
-                    r -= d.cls[c].nruns * d.cls[c].upr[pass];
-                    ++c;
+            int64_t first = 0;
+            for (int c = 0; c < d.ncls; ++c) {
+                const EnsClass<T>& cl = d.cls[c];
+                switch (cl.geo.n) {
+                    case 32: ens_class_pass<T, 32, V>(cl, pass, s > 0, d.modes[s], d.h, first, sm); break;
+                    case 48: ens_class_pass<T, 48, V>(cl, pass, s > 0, d.modes[s], d.h, first, sm); break;
+                    case 64: ens_class_pass<T, 64, V>(cl, pass, s > 0, d.modes[s], d.h, first, sm); break;
+                    default: ens_class_pass<T, 96, V>(cl, pass, s > 0, d.modes[s], d.h, first, sm); break;
                 }
-                const int64_t upr = d.cls[c].upr[pass];
-                ens_unit<T, V>(d.cls[c], pass, s > 0, d.modes[s], d.h, (int)(r / upr), r % upr, sm);
+                first += cl.nruns * cl.upr[pass];
             }
             if (!grid_barrier(d.bar, d.err, gridDim.x, d.spin_limit)) return;
         }
@@ -199,7 +211,7 @@ __global__ __launch_bounds__(ENS_NT) void k_ens_persistent(EnsDesc<T> d) {
 
 // one pass of one class, all its runs (BATCHED mode); blockIdx.x = unit
 template <typename T, int V>
-__global__ __launch_bounds__(ENS_NT) void k_ens_pass(EnsClass<T> c, int pass, int sv, int mode, T h) {
+__global__ __launch_bounds__(ENS_NT, 2) void k_ens_pass(EnsClass<T> c, int pass, int sv, int mode, T h) {
     __shared__ cx<T> sm[ens_lds<T>()];
     const int64_t upr = c.upr[pass];
     const int64_t u = blockIdx.x;
@@ -208,7 +220,7 @@ __global__ __launch_bounds__(ENS_NT) void k_ens_pass(EnsClass<T> c, int pass, in
 
 // one pass of one run (SEQUENTIAL mode)
 template <typename T, int V>
-__global__ __launch_bounds__(ENS_NT) void k_ens_pass_run(EnsClass<T> c, int pass, int sv, int mode, T h, int run) {
+__global__ __launch_bounds__(ENS_NT, 2) void k_ens_pass_run(EnsClass<T> c, int pass, int sv, int mode, T h, int run) {
     __shared__ cx<T> sm[ens_lds<T>()];
     ens_unit<T, V>(c, pass, sv, mode, h, run, blockIdx.x, sm);
 }
@@ -218,14 +230,14 @@ __global__ __launch_bounds__(ENS_NT) void k_ens_pass_run(EnsClass<T> c, int pass
 struct EnsKernels {
     void (*units)(const Geo&, int64_t*);
     const void* persistent;  // k_ens_persistent<float, V>
-    void (*launch_persistent)(const EnsDesc<float>&, int grid, hipStream_t);
+    void (*launch_persistent)(const EnsDesc<float>* dev_desc, int grid, hipStream_t);
     void (*launch_pass)(const EnsClass<float>&, int pass, int sv, int mode, float h, hipStream_t);
     void (*launch_pass_run)(const EnsClass<float>&, int pass, int sv, int mode, float h, int run, hipStream_t);
 };
 
 template <int V>
 struct EnsVariant {
-    static void launch_persistent(const EnsDesc<float>& d, int grid, hipStream_t s) {
+    static void launch_persistent(const EnsDesc<float>* d, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_ens_persistent<float, V>), dim3(grid), dim3(ENS_NT), 0, s, d);
     }
     static void launch_pass(const EnsClass<float>& c, int pass, int sv, int mode, float h, hipStream_t s) {

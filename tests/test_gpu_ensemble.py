@@ -113,8 +113,8 @@ def test_autotune_and_cache(P, init, tmp_path):
     assert ens.query()["variant"] == v
     ens2 = P.Ensemble(SIZES, rk_order=RK, nu=NU, dt=DT)
     assert ens2.autotune(path) == v        # served from the cache
-    assert ens2.query()["sizes"] == [32, 48, 64, 96]
-    assert ens2.query()["runs"] == [2, 2, 1, 1]
+    assert ens2.query()["sizes"] == [96, 64, 48, 32]
+    assert ens2.query()["runs"] == [1, 1, 2, 2]
 
 
 def test_ensemble_errors(P):
