@@ -474,7 +474,7 @@ extern "C" pst_status pst_fno_create(const pst_fno_params* p, void* hip_stream, 
     F->P = n * n * n;
     F->nxh = n / 2 + 1;
     F->nm = 4 * m * m * m;
-    F->fsz = (int64_t)n * n * F->nxh;
+    F->fsz = F->nm;  // compact spectra [batch][channel][mode]
     pst_params fp{n, PST_NS, PST_FP32, 4, 0.0, 0.0, 1.0, PST_DEALIAS_CUBE, 0};
     if (pst_plan_create(&fp, hip_stream, &F->fft) != PST_OK) {
         g_fno_err = std::string("transform plan: ") + pst_last_error(nullptr);
@@ -497,7 +497,8 @@ extern "C" pst_status pst_fno_create(const pst_fno_params* p, void* hip_stream, 
     off += 3 * H + 3;
     F->nparam = off;
     const int64_t act = (int64_t)B * W * F->P, pre = (int64_t)B * H * F->P, io = (int64_t)B * 3 * F->P;
-    const int64_t spec = (int64_t)B * W * F->fsz;
+    const int64_t spec = (int64_t)B * W * F->nm;
+    const int64_t wsp = (int64_t)B * W * n * n * m + (int64_t)B * W * n * 2 * m * m;  // pruned-transform workspace
     F->wpart_floats = (int64_t)1024 * 16 * 1024;  // blocks x tiles x 32 x 32 (upper bound used below)
     ok = ok && dmalloc((void**)&F->theta, 4 * off) && dmalloc((void**)&F->grad, 4 * off) &&
          dmalloc((void**)&F->am, 4 * off) && dmalloc((void**)&F->av, 4 * off) &&
@@ -507,7 +508,7 @@ extern "C" pst_status pst_fno_create(const pst_fno_params* p, void* hip_stream, 
          dmalloc((void**)&F->dv, 4 * act) && dmalloc((void**)&F->ds, 4 * act) && dmalloc((void**)&F->dpre, 4 * pre) &&
          dmalloc((void**)&F->dout, 4 * io) && dmalloc((void**)&F->tmp, 4 * act) &&
          dmalloc((void**)&F->specA, 8 * spec) && dmalloc((void**)&F->specB, 8 * spec) &&
-         dmalloc((void**)&F->ffttmp, 8 * spec) && dmalloc((void**)&F->vst, 8 * (int64_t)L * F->nm * B * W) &&
+         dmalloc((void**)&F->ffttmp, 8 * wsp) && dmalloc((void**)&F->vst, 8 * (int64_t)L * F->nm * B * W) &&
          dmalloc((void**)&F->part, 4 * F->wpart_floats) && dmalloc((void**)&F->lpart, sizeof(double) * 2 * 64 * 1024) &&
          dmalloc((void**)&F->coef, sizeof(float) * 64);
     if (!ok) {
@@ -515,20 +516,18 @@ extern "C" pst_status pst_fno_create(const pst_fno_params* p, void* hip_stream, 
         pst_fno_destroy(F);
         return PST_ERR_OOM;
     }
-    // retained modes: kx fastest in [0, m), then ky, then kz in [0, m) U [n - m, n)
+    // retained modes, in the order the pruned transforms produce them: kx fastest
+    // in [0, m), then ky, then kz, each in [0, m) U [n - m, n); the offset of a
+    // mode in a compact spectrum is its index.  Weight 1 on the kx = 0 plane
+    // (m <= n/2 keeps the Nyquist plane out), 2 elsewhere.
     std::vector<int> mo(F->nm);
     std::vector<float> mw(F->nm);
-    int i = 0;
-    for (int a = 0; a < 2 * m; ++a)
-        for (int c = 0; c < 2 * m; ++c)
-            for (int kx = 0; kx < m; ++kx, ++i) {
-                const int kz = a < m ? a : n - 2 * m + a, ky = c < m ? c : n - 2 * m + c;
-                mo[i] = (kz * n + ky) * F->nxh + kx;
-                mw[i] = (kx == 0 || 2 * kx == n) ? 1.f : 2.f;
-            }
+    for (int i = 0; i < F->nm; ++i) {
+        mo[i] = i;
+        mw[i] = (i % m == 0) ? 1.f : 2.f;
+    }
     hipMemcpy(F->modeoff, mo.data(), sizeof(int) * F->nm, hipMemcpyHostToDevice);
     hipMemcpy(F->modew, mw.data(), sizeof(float) * F->nm, hipMemcpyHostToDevice);
-    hipLaunchKernelGGL(k_fill0, dim3(gs(2 * spec)), dim3(256), 0, F->stream, (float*)F->specB, 2 * spec);
     hipLaunchKernelGGL(k_fill0, dim3(gs(off)), dim3(256), 0, F->stream, F->theta, off);
     hipLaunchKernelGGL(k_fill0, dim3(gs(off)), dim3(256), 0, F->stream, F->am, off);
     hipLaunchKernelGGL(k_fill0, dim3(gs(off)), dim3(256), 0, F->stream, F->av, off);
@@ -645,12 +644,12 @@ static void forward_pass(pst_fno* F, const float* u, int B, float* out) {
         float* vn = F->v + (l + 1) * astride;
         float* sl = F->s + l * astride;
         // spectral branch: kb = c2r(R . r2c(v))
-        F->fft->L->fft_r2c(F->fft, vl, F->specA, B * W);
+        F->fft->L->fft_r2c_modes(F->fft, vl, F->specA, B * W, F->p.modes, F->ffttmp);
         const size_t sh = sizeof(cx<float>) * ((size_t)B * W + (size_t)W * W);
         hipLaunchKernelGGL(k_mix_fwd, dim3(F->nm), dim3(GT), sh, F->stream, F->specA,
                            (const cx<float>*)(F->theta + F->offR[l]), F->modeoff, F->fsz, B, W, W, F->specB,
                            F->vst + (int64_t)l * F->nm * F->p.batch * W);
-        F->fft->L->fft_c2r(F->fft, F->specB, F->kb, B * W, F->ffttmp);
+        F->fft->L->fft_c2r_modes(F->fft, F->specB, F->kb, B * W, F->p.modes, F->ffttmp);
         const FnoDense& d = F->wc[l];
         const float* bias = F->theta + d.off + d.O * d.K;
         if (l < L - 1) dense_fwd(F, d, false, vl, B, bias, F->kb, nullptr, sl, vn, EPI_GELU, false);
@@ -718,12 +717,12 @@ extern "C" pst_status pst_fno_loss_grad(pst_fno* F, const float* u, const float*
         const FnoDense& d = F->wc[l];
         dense_grad(F, d, ds, vl, B, false);
         // spectral adjoint: S = r2c(ds); g_R; tmp = c2r(conj(R)^T S)
-        F->fft->L->fft_r2c(F->fft, ds, F->specA, B * W);
+        F->fft->L->fft_r2c_modes(F->fft, ds, F->specA, B * W, F->p.modes, F->ffttmp);
         const size_t sh = sizeof(cx<float>) * (2 * (size_t)B * W + (size_t)W * W);
         hipLaunchKernelGGL(k_mix_bwd, dim3(F->nm), dim3(GT), sh, F->stream, F->specA,
                            (const cx<float>*)(F->theta + F->offR[l]), F->vst + (int64_t)l * F->nm * F->p.batch * W,
                            F->modeoff, F->modew, F->fsz, B, W, W, P3, F->specB, (cx<float>*)(F->grad + F->offR[l]));
-        F->fft->L->fft_c2r(F->fft, F->specB, F->tmp, B * W, F->ffttmp);
+        F->fft->L->fft_c2r_modes(F->fft, F->specB, F->tmp, B * W, F->p.modes, F->ffttmp);
         // dv_l = Wc^T ds + tmp  (F->dv may alias ds for the last layer: write to a separate buffer)
         float* dst = (ds == F->dv) ? F->ds : F->dv;
         dense_fwd(F, d, true, ds, B, nullptr, F->tmp, nullptr, nullptr, dst, EPI_NONE, false);

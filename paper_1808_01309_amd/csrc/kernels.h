@@ -536,6 +536,120 @@ __global__ __launch_bounds__(NCfg<N>::G * tile_lines<T>()) void k_fft_strided(co
     }
 }
 
+// ------------------------------------------------------------ mode-pruned transforms
+// 3D r2c / c2r restricted to the box kx in [0, m), ky, kz in [0, m) U [N-m, N)
+// (compact index j < m <-> position j, j >= m <-> position j + N - 2m), laid
+// out [field][jz][jy][kx] (kx fastest).  Used by the spectral layers of the
+// neural operator.
+
+// x, forward, keep kx < m: out [lines][m]
+template <typename T, int N>
+__global__ __launch_bounds__(LINE_BLOCK) void k_fftx_r2c_m(const T* __restrict__ in, cx<T>* __restrict__ out,
+                                                            const cx<T>* __restrict__ tw, int64_t npairs, int m) {
+    using C = NCfg<N>;
+    using F = Fft<T, typename C::P, C::G, false>;
+    constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N);
+    __shared__ cx<T> sm[LPB * LS];
+    const int l = threadIdx.x / G, g = threadIdx.x % G;
+    const int64_t pair = (int64_t)blockIdx.x * LPB + l;
+    const bool active = pair < npairs;
+    const LineLds<T> lds{sm + l * LS};
+    const T* a = in + 2 * pair * N;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = F::first_pos(g, e);
+        v[e] = active ? cx<T>{a[p], a[N + p]} : czero<T>();
+    }
+    F::run(v, g, lds, tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds(F::last_pos(g, e)) = v[e];
+    __syncthreads();
+    if (!active) return;
+    cx<T>* oa = out + 2 * pair * m;
+    for (int k = g; k < m; k += G) {
+        const cx<T> z1 = lds(k), z2 = lds(k == 0 ? 0 : N - k);
+        oa[k] = {T(0.5) * (z1.x + z2.x), T(0.5) * (z1.y - z2.y)};
+        oa[m + k] = {T(0.5) * (z1.y + z2.y), T(-0.5) * (z1.x - z2.x)};
+    }
+}
+
+// x, backward from kx < m (Hermitian extension, imaginary part of kx = 0 dropped)
+template <typename T, int N>
+__global__ __launch_bounds__(LINE_BLOCK) void k_fftx_c2r_m(const cx<T>* __restrict__ in, T* __restrict__ out,
+                                                            const cx<T>* __restrict__ tw, int64_t npairs, int m) {
+    using C = NCfg<N>;
+    using F = Fft<T, typename C::P, C::G, true>;
+    constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N);
+    __shared__ cx<T> sm[LPB * LS];
+    const int l = threadIdx.x / G, g = threadIdx.x % G;
+    const int64_t pair = (int64_t)blockIdx.x * LPB + l;
+    const bool active = pair < npairs;
+    const LineLds<T> lds{sm + l * LS};
+    const cx<T>* ia = in + 2 * pair * m;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = F::first_pos(g, e);
+        cx<T> Z = czero<T>();
+        if (active) {
+            if (p == 0) {
+                Z = {ia[0].x, ia[m].x};
+            } else if (p < m) {
+                const cx<T> A = ia[p], B = ia[m + p];
+                Z = {A.x - B.y, A.y + B.x};
+            } else if (p > N - m) {
+                const cx<T> A = ia[N - p], B = ia[m + N - p];
+                Z = {A.x + B.y, B.x - A.y};
+            }
+        }
+        v[e] = Z;
+    }
+    F::run(v, g, lds, tw);
+    if (!active) return;
+    T* oa = out + 2 * pair * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int q = F::last_pos(g, e);
+        oa[q] = v[e].x;
+        oa[N + q] = v[e].y;
+    }
+}
+
+// Strided pass over TL consecutive columns of a plane (blockIdx.y); rows are
+// either all N positions (row p at p * rs) or the 2m retained ones (row j at
+// j * rs), separately for input (PIN) and output (POUT).
+template <typename T, int N, bool INV, bool PIN, bool POUT>
+__global__ __launch_bounds__(NCfg<N>::G * tile_lines<T>()) void k_fft_cols_m(
+    const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw, int64_t ncols, int64_t rs_in,
+    int64_t ps_in, int64_t rs_out, int64_t ps_out, int m, T scale) {
+    using C = NCfg<N>;
+    using F = Fft<T, typename C::P, C::G, INV>;
+    constexpr int G = C::G, E = F::E, TL = tile_lines<T>(), TLP = TL + 1;
+    __shared__ cx<T> sm[N * TLP];
+    const int t = threadIdx.x % TL, g = threadIdx.x / TL;
+    const int64_t col = (int64_t)blockIdx.x * TL + t;
+    const bool cin = col < ncols;
+    const cx<T>* src = in + (int64_t)blockIdx.y * ps_in + col;
+    cx<T>* dst = out + (int64_t)blockIdx.y * ps_out + col;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int p = F::first_pos(g, e);
+        const int row = PIN ? (p < m ? p : (p >= N - m ? p - (N - 2 * m) : -1)) : p;
+        v[e] = (cin && row >= 0) ? src[row * rs_in] : czero<T>();
+    }
+    F::run(v, g, TileLds<T, TLP>{sm + t}, tw);
+    if (cin) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int q = F::last_pos(g, e);
+            const int row = POUT ? (q < m ? q : (q >= N - m ? q - (N - 2 * m) : -1)) : q;
+            if (row >= 0) dst[row * rs_out] = cscale(v[e], scale);
+        }
+    }
+}
+
 // ------------------------------------------------------------ launchers
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
@@ -654,6 +768,53 @@ struct Impl {
         }
     }
 
+    // workspace: nf N N m + nf N 2m m complex
+    static void fft_r2c_modes(pst_plan* P, const void* in, void* out, int nf, int m, void* tmp) {
+        const int64_t npairs = (int64_t)nf * N * N / 2, m2 = 2 * m;
+        cx<T>* t1 = (cx<T>*)tmp;                       // [nf][z][y][kx < m]
+        cx<T>* t2 = t1 + (int64_t)nf * N * N * m;      // [nf][z][jy][kx]
+        {
+            KTimer tm(P, PST_K_FFTX);
+            hipLaunchKernelGGL((k_fftx_r2c_m<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                               P->stream, (const T*)in, t1, (const cx<T>*)P->tw, npairs, m);
+        }
+        {
+            KTimer tm(P, PST_K_FFTY);
+            hipLaunchKernelGGL((k_fft_cols_m<T, N, false, false, true>), dim3(cdiv(m, TL), (unsigned)(nf * N)),
+                               dim3(TB), 0, P->stream, t1, t2, (const cx<T>*)P->tw, (int64_t)m, (int64_t)m,
+                               (int64_t)N * m, (int64_t)m, m2 * m, m, T(1));
+        }
+        {
+            KTimer tm(P, PST_K_FFTZ);
+            const T s = T(1) / (T(N) * T(N) * T(N));
+            hipLaunchKernelGGL((k_fft_cols_m<T, N, false, false, true>), dim3(cdiv(m2 * m, TL), (unsigned)nf),
+                               dim3(TB), 0, P->stream, t2, (cx<T>*)out, (const cx<T>*)P->tw, m2 * m, m2 * m,
+                               (int64_t)N * m2 * m, m2 * m, m2 * m2 * m, m, s);
+        }
+    }
+    static void fft_c2r_modes(pst_plan* P, const void* in, void* out, int nf, int m, void* tmp) {
+        const int64_t npairs = (int64_t)nf * N * N / 2, m2 = 2 * m;
+        cx<T>* t1 = (cx<T>*)tmp;
+        cx<T>* t2 = t1 + (int64_t)nf * N * N * m;
+        {
+            KTimer tm(P, PST_K_FFTZ);
+            hipLaunchKernelGGL((k_fft_cols_m<T, N, true, true, false>), dim3(cdiv(m2 * m, TL), (unsigned)nf),
+                               dim3(TB), 0, P->stream, (const cx<T>*)in, t2, (const cx<T>*)P->tw, m2 * m, m2 * m,
+                               m2 * m2 * m, m2 * m, (int64_t)N * m2 * m, m, T(1));
+        }
+        {
+            KTimer tm(P, PST_K_FFTY);
+            hipLaunchKernelGGL((k_fft_cols_m<T, N, true, true, false>), dim3(cdiv(m, TL), (unsigned)(nf * N)),
+                               dim3(TB), 0, P->stream, t2, t1, (const cx<T>*)P->tw, (int64_t)m, (int64_t)m, m2 * m,
+                               (int64_t)m, (int64_t)N * m, m, T(1));
+        }
+        {
+            KTimer tm(P, PST_K_FFTX);
+            hipLaunchKernelGGL((k_fftx_c2r_m<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                               P->stream, t1, (T*)out, (const cx<T>*)P->tw, npairs, m);
+        }
+    }
+
     static const Launchers* get() {
         static Launchers L = [] {
             Launchers l{};
@@ -667,6 +828,8 @@ struct Impl {
             l.zfwd = &zfwd;
             l.fft_r2c = &fft_r2c;
             l.fft_c2r = &fft_c2r;
+            l.fft_r2c_modes = &fft_r2c_modes;
+            l.fft_c2r_modes = &fft_c2r_modes;
             return l;
         }();
         return &L;

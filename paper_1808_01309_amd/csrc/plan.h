@@ -97,6 +97,10 @@ struct Launchers {
     void (*zfwd)(pst_plan*, int mode, void* rhs_out);
     void (*fft_r2c)(pst_plan*, const void* in, void* out, int nf);
     void (*fft_c2r)(pst_plan*, const void* in, void* out, int nf, void* tmp);
+    // transforms restricted to the retained-mode box (kx < m, ky, kz in [0, m) U [n-m, n)),
+    // compact spectra [nf][2m][2m][m]; workspace nf n n m + nf n 2m m complex
+    void (*fft_r2c_modes)(pst_plan*, const void* in, void* out, int nf, int m, void* tmp);
+    void (*fft_c2r_modes)(pst_plan*, const void* in, void* out, int nf, int m, void* tmp);
 };
 
 const Launchers* launchers_for(int n, int precision);

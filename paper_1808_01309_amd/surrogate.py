@@ -44,6 +44,7 @@ def generate(nseeds, n=64, steps=510, seed0=1000, nu=1e-2, dt=1e-3, rk=4, spectr
     """Solver trajectories: float32 device tensor [nseeds][steps + 1][3][n][n][n]."""
     import torch
     ens = pst.Ensemble([n] * nseeds, rk_order=rk, nu=nu, dt=dt)
+    ens.set_mode("batched")
     for s in range(nseeds):
         ens.set_state(s, I.random_solenoidal(n, seed0 + s, spectrum=spectrum, dtype=np.complex64))
     conv = Converter(n)
@@ -91,8 +92,9 @@ class _Stage:
     """An ensemble plus the buffers to move its states to and from physical space
     (one transform call for all runs)."""
 
-    def __init__(self, sizes, nu, dt, rk, conv):
+    def __init__(self, sizes, nu, dt, rk, conv, mode="batched"):
         self.ens = pst.Ensemble(sizes, rk_order=rk, nu=nu, dt=dt)
+        self.ens.set_mode(mode)   # the fastest execution mode of the solver
         self.conv = conv
         self.nb = len(sizes)
 
