@@ -24,29 +24,11 @@
 #include <string>
 #include <vector>
 
-#include "fft_engine.h"
-#include "plan.h"
+#include "fno_internal.h"
 
 using namespace pst;
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
 namespace {
-
-constexpr int GT = 256;  // threads per block of the FNO kernels
-
-__device__ __forceinline__ unsigned short f2bf(float f) {
-    // round to nearest even (inputs are finite)
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
-
-__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad_f(float x) {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
-}
 
 enum { EPI_NONE = 0, EPI_GELU = 1, EPI_DGELU = 2 };
 
@@ -212,7 +194,7 @@ __global__ __launch_bounds__(GT) void k_mix_fwd(const cx<float>* __restrict__ sp
     for (int i = threadIdx.x; i < B * C; i += GT) {
         const cx<float> v = spec_in[(int64_t)i * fsz + off];
         Vh[i] = v;
-        vstore[(int64_t)m * B * C + i] = v;
+        if (vstore) vstore[(int64_t)m * B * C + i] = v;
     }
     for (int i = threadIdx.x; i < C * O; i += GT) Rm[i] = R[(int64_t)m * C * O + i];
     __syncthreads();
@@ -361,34 +343,6 @@ unsigned gs(int64_t n) {
 }  // namespace
 
 // =================================================================== host side
-struct FnoDense {
-    int O, K, Opad, Kpad, To, Tk;   // To x Tk: transposed padded shape
-    int64_t off;                    // offset of W in theta (bias follows at off + O K)
-    unsigned short *Wb, *Tb;
-    float *Wf, *Tf;
-};
-
-struct pst_fno {
-    pst_fno_params p;
-    hipStream_t stream;
-    pst_plan* fft;            // transform plan of size n (its FFT kernels)
-    int P, nxh, nm;
-    int64_t fsz, nparam;
-    float *theta, *grad, *am, *av;
-    int64_t adam_t;
-    FnoDense lift, wc[8], q1, q2;
-    int64_t offR[8];
-    int *modeoff;
-    float* modew;
-    float *v, *s, *kb, *pre, *out, *dv, *ds, *dpre, *dout, *tmp;
-    cx<float> *specA, *specB, *ffttmp, *vst;
-    float* part;
-    double* lpart;
-    float* coef;
-    int64_t wpart_floats;
-    std::string msg;
-};
-
 static thread_local std::string g_fno_err;
 
 static pst_status ffail(pst_fno* F, pst_status s, const char* fmt, ...) {
@@ -663,10 +617,31 @@ static void forward_pass(pst_fno* F, const float* u, int B, float* out) {
               true);
 }
 
+// Inference forward on the fused layer kernels: activations ping-pong between
+// two slots of F->v (BF16 on the matrix-core path), the x-transformed lines of
+// the spectral branch stay in the transform workspace between kernels.
+static void forward_fused(pst_fno* F, const float* u, int B, float* out) {
+    const int W = F->p.width, L = F->p.layers, m = F->p.modes;
+    const int64_t astride = (int64_t)F->p.batch * W * F->P;
+    void* act[2] = {F->v, F->v + astride};
+    fno_fused_lift(F, u, B, act[0], F->ffttmp);
+    const size_t sh = sizeof(cx<float>) * ((size_t)B * W + (size_t)W * W);
+    for (int l = 0; l < L; ++l) {
+        F->fft->L->modes_yz_fwd(F->fft, F->specA, B * W, m, F->ffttmp);
+        hipLaunchKernelGGL(k_mix_fwd, dim3(F->nm), dim3(GT), sh, F->stream, F->specA,
+                           (const cx<float>*)(F->theta + F->offR[l]), F->modeoff, F->fsz, B, W, W, F->specB,
+                           (cx<float>*)nullptr);
+        F->fft->L->modes_yz_inv(F->fft, F->specB, B * W, m, F->ffttmp);
+        if (l < L - 1) fno_fused_layer(F, l, B, act[l & 1], act[(l + 1) & 1], F->ffttmp);
+        else fno_fused_last(F, l, B, act[l & 1], F->ffttmp, u, out);
+    }
+}
+
 extern "C" pst_status pst_fno_forward(pst_fno* F, const float* u, float* out, int batch) {
     if (!F) return PST_ERR_INVALID_ARG;
     if (!u || !out || batch < 1 || batch > F->p.batch) return ffail(F, PST_ERR_INVALID_ARG, "bad buffers or batch");
-    forward_pass(F, u, batch, out);
+    if (fno_fused_supported(F->p.n)) forward_fused(F, u, batch, out);
+    else forward_pass(F, u, batch, out);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? PST_OK : ffail(F, PST_ERR_HIP, "launch failed: %s", hipGetErrorString(e));
 }

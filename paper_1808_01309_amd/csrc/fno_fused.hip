@@ -1,0 +1,359 @@
+// Fused inference kernels of the Fourier neural operator.
+//
+// A layer is  s = Wc v + b + K(v),  K(v) = c2r(R . r2c(v) on the retained
+// modes).  The y and z passes of the pruned transforms and the per-mode mixing
+// need whole planes and run as separate kernels; everything that is local to
+// one x line runs in one kernel per layer, over blocks of RB consecutive
+// (b, z, y) rows and all channels:
+//
+//   x c2r of the spectral branch (t1 -> LDS)  ->  channel mixing Wc v on the
+//   matrix cores (BF16 operands, FP32 accumulation; FP32 FMA variant)  ->
+//   + bias + spectral branch, GELU  ->  store v_{l+1}  ->  x r2c of v_{l+1}
+//   keeping kx < m (LDS -> t1, in place: a block reads and writes only its
+//   own rows).
+//
+// The first kernel applies the lift instead of a layer; the last fuses the
+// projection 32 -> hidden -> GELU -> 3 and the residual, so v_L and the hidden
+// activations never reach HBM.  Between layers the activations are stored in
+// BF16 on the matrix-core path (exactly the values its MFMA operands take) and
+// FP32 otherwise; the spectral branch always transforms the FP32 values.
+#include "fno_internal.h"
+#include "kernels.h"
+
+namespace pst {
+namespace {
+
+constexpr int FT = 256;  // threads per block
+
+// rows per block: RB n points, a multiple of 32 (one MFMA tile), n % RB == 0
+template <int N> constexpr int fno_rows() { return N <= 16 ? 8 : (N <= 32 ? 4 : (N <= 64 ? 2 : 1)); }
+
+template <bool BF> struct Act;
+template <> struct Act<true> {
+    using T = unsigned short;
+    __device__ __forceinline__ static void st(T* p, int64_t i, float x) { p[i] = f2bf(x); }
+};
+template <> struct Act<false> {
+    using T = float;
+    __device__ __forceinline__ static void st(T* p, int64_t i, float x) { p[i] = x; }
+};
+
+// bytes of dynamic LDS: X [W][RB n] floats, then one FFT line scratch per pair slot
+template <int N> size_t fused_lds(int W) {
+    return sizeof(float) * (size_t)W * fno_rows<N>() * N +
+           sizeof(cx<float>) * (size_t)(FT / NCfg<N>::G) * LineLds<float>::size(N);
+}
+
+// Block geometry: blockIdx.x = (b N + z) (N / RB) + yb, first point p0 of the
+// block in a field, lines l = r W + c (row r, channel c) live at X[c][r N + x].
+struct RowBlock {
+    int b, z, y0;
+    int64_t p0;
+};
+template <int N> __device__ __forceinline__ RowBlock row_block() {
+    constexpr int RB = fno_rows<N>();
+    RowBlock r;
+    const int yb = blockIdx.x % (N / RB), bz = blockIdx.x / (N / RB);
+    r.z = bz % N;
+    r.b = bz / N;
+    r.y0 = yb * RB;
+    r.p0 = ((int64_t)r.z * N + r.y0) * N;
+    return r;
+}
+template <int N> __device__ __forceinline__ int64_t t1_line(const RowBlock& rb, int W, int m, int l) {
+    const int r = l / W, c = l % W;
+    return ((((int64_t)rb.b * W + c) * N + rb.z) * N + rb.y0 + r) * m;
+}
+
+// x r2c of the block's RB W lines held in X, keeping kx < m, into t1.
+// Lines are transformed in pairs (2i, 2i + 1) packed as one complex line.
+template <int N>
+__device__ __forceinline__ void rows_r2c(const float* X, int W, int m, const RowBlock& rb, cx<float>* __restrict__ t1,
+                                         const cx<float>* __restrict__ tw, cx<float>* fl) {
+    using C = NCfg<N>;
+    using F = Fft<float, typename C::P, C::G, false>;
+    constexpr int G = C::G, E = F::E, NPG = FT / G, LS = LineLds<float>::size(N), PB = fno_rows<N>() * N;
+    const int g = threadIdx.x % G, li = threadIdx.x / G;
+    const LineLds<float> lds{fl + li * LS};
+    const int NL = fno_rows<N>() * W, npair = (NL + 1) / 2;
+    for (int base = 0; base < npair; base += NPG) {  // same trip count in every thread
+        const int l0 = 2 * (base + li), l1 = l0 + 1;
+        const bool a0 = l0 < NL, a1 = l1 < NL;
+        const float* x0 = X + (a0 ? (l0 % W) * PB + (l0 / W) * N : 0);
+        const float* x1 = X + (a1 ? (l1 % W) * PB + (l1 / W) * N : 0);
+        cx<float> v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = F::first_pos(g, e);
+            v[e] = {a0 ? x0[p] : 0.f, a1 ? x1[p] : 0.f};
+        }
+        F::run(v, g, lds, tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds(F::last_pos(g, e)) = v[e];
+        __syncthreads();
+        cx<float>* o0 = t1 + (a0 ? t1_line<N>(rb, W, m, l0) : 0);
+        cx<float>* o1 = t1 + (a1 ? t1_line<N>(rb, W, m, l1) : 0);
+        for (int k = g; k < m; k += G) {
+            const cx<float> z1 = lds(k), z2 = lds(k == 0 ? 0 : N - k);
+            if (a0) o0[k] = {0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y)};
+            if (a1) o1[k] = {0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x)};
+        }
+        __syncthreads();  // the scratch is rewritten by the next pair
+    }
+}
+
+// x c2r of the block's lines from t1 (kx < m, Hermitian extension, imaginary
+// part of kx = 0 dropped) into X.
+template <int N>
+__device__ __forceinline__ void rows_c2r(const cx<float>* __restrict__ t1, int W, int m, const RowBlock& rb, float* X,
+                                         const cx<float>* __restrict__ tw, cx<float>* fl) {
+    using C = NCfg<N>;
+    using F = Fft<float, typename C::P, C::G, true>;
+    constexpr int G = C::G, E = F::E, NPG = FT / G, LS = LineLds<float>::size(N), PB = fno_rows<N>() * N;
+    const int g = threadIdx.x % G, li = threadIdx.x / G;
+    const LineLds<float> lds{fl + li * LS};
+    const int NL = fno_rows<N>() * W, npair = (NL + 1) / 2;
+    for (int base = 0; base < npair; base += NPG) {
+        const int l0 = 2 * (base + li), l1 = l0 + 1;
+        const bool a0 = l0 < NL, a1 = l1 < NL;
+        const cx<float>* i0 = t1 + (a0 ? t1_line<N>(rb, W, m, l0) : 0);
+        const cx<float>* i1 = t1 + (a1 ? t1_line<N>(rb, W, m, l1) : 0);
+        cx<float> v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int p = F::first_pos(g, e);
+            const int k = p < m ? p : (p > N - m ? N - p : -1);
+            cx<float> A = czero<float>(), B = czero<float>();
+            if (k >= 0) {
+                if (a0) A = i0[k];
+                if (a1) B = i1[k];
+            }
+            if (p == 0) v[e] = {A.x, B.x};
+            else if (p < m) v[e] = {A.x - B.y, A.y + B.x};
+            else v[e] = {A.x + B.y, B.x - A.y};  // zero when k < 0
+        }
+        F::run(v, g, lds, tw);
+        float* x0 = X + (a0 ? (l0 % W) * PB + (l0 / W) * N : 0);
+        float* x1 = X + (a1 ? (l1 % W) * PB + (l1 / W) * N : 0);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int q = F::last_pos(g, e);
+            if (a0) x0[q] = v[e].x;
+            if (a1) x1[q] = v[e].y;
+        }
+        // the transform's last LDS reads precede its final barrier: the
+        // scratch can be rewritten by the next pair without another one
+    }
+}
+
+// acc[r] = sum_k W[ot 32 + m(r)][k] x[k][n] over k < K for this lane's point n,
+// the MFMA 32x32x8 register layout: m(r) = 8 (r / 4) + 4 kg + r % 4.
+// x comes from a column of a channel-major array (element stride xs).
+template <bool MFMA, typename XT>
+__device__ __forceinline__ f32x16 mix_tile(const unsigned short* __restrict__ Wb, const float* __restrict__ Wf,
+                                           int Kpad, int K, int ot, const XT* x, int64_t xs, int n, int kg) {
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    if constexpr (MFMA) {
+        const unsigned short* wrow = Wb + (int64_t)(ot * 32 + n) * Kpad + 4 * kg;
+        for (int s = 0; s < Kpad / 8; ++s) {
+            bf16x4 aa, bb;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 8 * s + 4 * kg + j;
+                if constexpr (sizeof(XT) == 2) bb[j] = k < K ? (short)x[k * xs] : (short)0;
+                else bb[j] = k < K ? (short)f2bf(x[k * xs]) : (short)0;
+                aa[j] = (short)wrow[8 * s + j];
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aa, bb, acc, 0, 0, 0);
+        }
+    } else {
+        for (int k = 0; k < K; ++k) {
+            const float xv = (float)x[k * xs];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int mm = 8 * (r / 4) + 4 * kg + (r % 4);
+                acc[r] += Wf[(int64_t)(ot * 32 + mm) * Kpad + k] * xv;
+            }
+        }
+    }
+    return acc;
+}
+
+template <int N, bool BF>
+__global__ __launch_bounds__(FT) void k_fno_lift(const float* __restrict__ u, const float* __restrict__ Wl,
+                                                 const float* __restrict__ bl, int W, int m,
+                                                 typename Act<BF>::T* __restrict__ vout, cx<float>* __restrict__ t1,
+                                                 const cx<float>* __restrict__ tw) {
+    constexpr int PB = fno_rows<N>() * N;
+    constexpr int64_t P3 = (int64_t)N * N * N;
+    extern __shared__ float X[];
+    cx<float>* fl = (cx<float>*)(X + W * PB);
+    const RowBlock rb = row_block<N>();
+    const float* ub = u + (int64_t)rb.b * 3 * P3 + rb.p0;
+    for (int i = threadIdx.x; i < W * PB; i += FT) {
+        const int o = i / PB, pt = i % PB;
+        const float s = bl[o] + Wl[3 * o] * ub[pt] + Wl[3 * o + 1] * ub[P3 + pt] + Wl[3 * o + 2] * ub[2 * P3 + pt];
+        X[i] = s;
+        Act<BF>::st(vout, ((int64_t)rb.b * W + o) * P3 + rb.p0 + pt, s);
+    }
+    __syncthreads();
+    rows_r2c<N>(X, W, m, rb, t1, tw, fl);
+}
+
+struct ProjArgs {
+    const unsigned short* Wb;  // Wq1 padded [Hpad][Kpad] BF16
+    const float* Wf;           // same, FP32
+    int Kpad, H, Hpad;
+    const float *bq1, *Wq2, *bq2;  // Wq2 [3][H]
+    const float* u;
+    float* out;
+};
+
+template <int N, bool BF, bool LAST>
+__global__ __launch_bounds__(FT) void k_fno_layer(const typename Act<BF>::T* __restrict__ vin,
+                                                  const unsigned short* __restrict__ Wb, const float* __restrict__ Wf,
+                                                  int Kpad, int Opad, const float* __restrict__ bias, int W, int m,
+                                                  typename Act<BF>::T* __restrict__ vout, cx<float>* __restrict__ t1,
+                                                  const cx<float>* __restrict__ tw, ProjArgs pa) {
+    constexpr int PB = fno_rows<N>() * N, PT = PB / 32;
+    constexpr int64_t P3 = (int64_t)N * N * N;
+    extern __shared__ float X[];
+    cx<float>* fl = (cx<float>*)(X + W * PB);
+    const RowBlock rb = row_block<N>();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 31, kg = lane >> 5;
+
+    // spectral branch of every line of the block
+    rows_c2r<N>(t1, W, m, rb, X, tw, fl);
+    __syncthreads();
+
+    // channel mixing + bias + spectral branch (+ GELU), tiles of 32 channels x 32 points
+    const int ntile = (Opad / 32) * PT;
+    for (int t = wave; t < ntile; t += FT / 64) {
+        const int ot = t / PT, pt0 = (t % PT) * 32;
+        const f32x16 acc = mix_tile<BF>(Wb, Wf, Kpad, W, ot, vin + (int64_t)rb.b * W * P3 + rb.p0 + pt0 + n, P3, n, kg);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int o = ot * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
+            if (o >= W) continue;
+            float* xo = X + o * PB + pt0 + n;
+            float s = acc[r] + bias[o] + *xo;
+            if (!LAST) {
+                s = gelu_f(s);
+                Act<BF>::st(vout, ((int64_t)rb.b * W + o) * P3 + rb.p0 + pt0 + n, s);
+            }
+            *xo = s;  // this lane is the only reader and writer of X[o][pt]
+        }
+    }
+    __syncthreads();
+
+    if constexpr (!LAST) {
+        rows_r2c<N>(X, W, m, rb, t1, tw, fl);
+    } else {
+        // projection: out = u + Wq2 gelu(Wq1 v + bq1) + bq2, one 32-point tile per wave
+        for (int t = wave; t < PT; t += FT / 64) {
+            const int pt0 = t * 32;
+            float y0 = 0.f, y1 = 0.f, y2 = 0.f;
+            for (int ht = 0; ht < pa.Hpad / 32; ++ht) {
+                const f32x16 acc = mix_tile<BF>(pa.Wb, pa.Wf, pa.Kpad, W, ht, X + pt0 + n, (int64_t)PB, n, kg);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int h = ht * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
+                    if (h >= pa.H) continue;
+                    const float a = gelu_f(acc[r] + pa.bq1[h]);
+                    y0 += pa.Wq2[h] * a;
+                    y1 += pa.Wq2[pa.H + h] * a;
+                    y2 += pa.Wq2[2 * pa.H + h] * a;
+                }
+            }
+            // the two half-waves hold disjoint hidden units of the same points
+            y0 += __shfl_xor(y0, 32);
+            y1 += __shfl_xor(y1, 32);
+            y2 += __shfl_xor(y2, 32);
+            if (kg == 0) {
+                const int64_t i0 = (int64_t)rb.b * 3 * P3 + rb.p0 + pt0 + n;
+                pa.out[i0] = pa.u[i0] + y0 + pa.bq2[0];
+                pa.out[i0 + P3] = pa.u[i0 + P3] + y1 + pa.bq2[1];
+                pa.out[i0 + 2 * P3] = pa.u[i0 + 2 * P3] + y2 + pa.bq2[2];
+            }
+        }
+    }
+}
+
+template <int N>
+struct Fused {
+    static unsigned grid(int B) { return (unsigned)(B * N * (N / fno_rows<N>())); }
+    static void lift(pst_fno* F, const float* u, int B, void* act, cx<float>* t1) {
+        const int W = F->p.width;
+        const float* Wl = F->theta + F->lift.off;
+        const cx<float>* tw = (const cx<float>*)F->fft->tw;
+        if (F->p.mfma)
+            hipLaunchKernelGGL((k_fno_lift<N, true>), dim3(grid(B)), dim3(FT), fused_lds<N>(W), F->stream, u, Wl,
+                               Wl + 3 * W, W, F->p.modes, (unsigned short*)act, t1, tw);
+        else
+            hipLaunchKernelGGL((k_fno_lift<N, false>), dim3(grid(B)), dim3(FT), fused_lds<N>(W), F->stream, u, Wl,
+                               Wl + 3 * W, W, F->p.modes, (float*)act, t1, tw);
+    }
+    template <bool LAST>
+    static void layer(pst_fno* F, int l, int B, const void* ain, void* aout, cx<float>* t1, const float* u, float* out) {
+        const int W = F->p.width;
+        const FnoDense& d = F->wc[l];
+        const float* bias = F->theta + d.off + (int64_t)d.O * d.K;
+        const cx<float>* tw = (const cx<float>*)F->fft->tw;
+        ProjArgs pa{};
+        if (LAST) {
+            const FnoDense& q1 = F->q1;
+            const FnoDense& q2 = F->q2;
+            pa.Wb = q1.Wb;
+            pa.Wf = q1.Wf;
+            pa.Kpad = q1.Kpad;
+            pa.H = q1.O;
+            pa.Hpad = q1.Opad;
+            pa.bq1 = F->theta + q1.off + (int64_t)q1.O * q1.K;
+            pa.Wq2 = F->theta + q2.off;
+            pa.bq2 = F->theta + q2.off + (int64_t)q2.O * q2.K;
+            pa.u = u;
+            pa.out = out;
+        }
+        if (F->p.mfma)
+            hipLaunchKernelGGL((k_fno_layer<N, true, LAST>), dim3(grid(B)), dim3(FT), fused_lds<N>(W), F->stream,
+                               (const unsigned short*)ain, d.Wb, d.Wf, d.Kpad, d.Opad, bias, W, F->p.modes,
+                               (unsigned short*)aout, t1, tw, pa);
+        else
+            hipLaunchKernelGGL((k_fno_layer<N, false, LAST>), dim3(grid(B)), dim3(FT), fused_lds<N>(W), F->stream,
+                               (const float*)ain, d.Wb, d.Wf, d.Kpad, d.Opad, bias, W, F->p.modes, (float*)aout, t1, tw,
+                               pa);
+    }
+};
+
+}  // namespace
+
+#define FNO_FUSED_SIZES(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
+
+bool fno_fused_supported(int n) {
+#define FNO_CASE(N) if (n == N) return true;
+    FNO_FUSED_SIZES(FNO_CASE)
+#undef FNO_CASE
+    return false;
+}
+
+void fno_fused_lift(pst_fno* F, const float* u, int B, void* act, cx<float>* t1) {
+#define FNO_CASE(N) if (F->p.n == N) return Fused<N>::lift(F, u, B, act, t1);
+    FNO_FUSED_SIZES(FNO_CASE)
+#undef FNO_CASE
+}
+
+void fno_fused_layer(pst_fno* F, int l, int B, const void* act_in, void* act_out, cx<float>* t1) {
+#define FNO_CASE(N) if (F->p.n == N) return Fused<N>::template layer<false>(F, l, B, act_in, act_out, t1, nullptr, nullptr);
+    FNO_FUSED_SIZES(FNO_CASE)
+#undef FNO_CASE
+}
+
+void fno_fused_last(pst_fno* F, int l, int B, const void* act_in, cx<float>* t1, const float* u, float* out) {
+#define FNO_CASE(N) if (F->p.n == N) return Fused<N>::template layer<true>(F, l, B, act_in, nullptr, t1, u, out);
+    FNO_FUSED_SIZES(FNO_CASE)
+#undef FNO_CASE
+}
+
+}  // namespace pst

@@ -1,0 +1,78 @@
+// Definitions shared by the neural-operator translation units: the operator's
+// host state, BF16 rounding, GELU, and the fused inference kernels' entry
+// points (one kernel per layer, see fno_fused.hip).
+#pragma once
+#include <math.h>
+
+#include <string>
+
+#include "fft_engine.h"
+#include "plan.h"
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+namespace pst {
+
+constexpr int GT = 256;  // threads per block of the FNO kernels
+
+// FP32 -> BF16, round to nearest even (inputs are finite)
+__device__ __forceinline__ unsigned short f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// exact-erf GELU and its derivative
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+}  // namespace pst
+
+// A dense (pointwise) layer W [O][K] + b: offsets into the parameter vector and
+// padded BF16 / FP32 copies of W and of its transpose.
+struct FnoDense {
+    int O, K, Opad, Kpad, To, Tk;   // To x Tk: transposed padded shape
+    int64_t off;                    // offset of W in theta (bias follows at off + O K)
+    unsigned short *Wb, *Tb;
+    float *Wf, *Tf;
+};
+
+struct pst_fno {
+    pst_fno_params p;
+    hipStream_t stream;
+    pst_plan* fft;            // transform plan of size n (its FFT kernels)
+    int P, nxh, nm;
+    int64_t fsz, nparam;
+    float *theta, *grad, *am, *av;
+    int64_t adam_t;
+    FnoDense lift, wc[8], q1, q2;
+    int64_t offR[8];
+    int *modeoff;
+    float* modew;
+    float *v, *s, *kb, *pre, *out, *dv, *ds, *dpre, *dout, *tmp;
+    pst::cx<float> *specA, *specB, *ffttmp, *vst;
+    float* part;
+    double* lpart;
+    float* coef;
+    int64_t wpart_floats;
+    std::string msg;
+};
+
+namespace pst {
+
+// Fused inference kernels (grid sizes n with an instantiation; false otherwise).
+// Activations between layers are BF16 when the operator runs on the matrix
+// cores, FP32 otherwise; t1 holds the x-transformed lines [b][c][z][y][kx < m].
+bool fno_fused_supported(int n);
+//   v0 = lift(u) -> act, x r2c of v0 -> t1
+void fno_fused_lift(pst_fno* F, const float* u, int B, void* act, cx<float>* t1);
+//   s = Wc_l v_l + b_l + x c2r(t1); v_{l+1} = gelu(s) -> act_out, x r2c(v_{l+1}) -> t1 (in place)
+void fno_fused_layer(pst_fno* F, int l, int B, const void* act_in, void* act_out, cx<float>* t1);
+//   last layer (no activation) and projection: out = u + Wq2 gelu(Wq1 v_L + bq1) + bq2
+void fno_fused_last(pst_fno* F, int l, int B, const void* act_in, cx<float>* t1, const float* u, float* out);
+
+}  // namespace pst

@@ -768,16 +768,12 @@ struct Impl {
         }
     }
 
-    // workspace: nf N N m + nf N 2m m complex
-    static void fft_r2c_modes(pst_plan* P, const void* in, void* out, int nf, int m, void* tmp) {
-        const int64_t npairs = (int64_t)nf * N * N / 2, m2 = 2 * m;
-        cx<T>* t1 = (cx<T>*)tmp;                       // [nf][z][y][kx < m]
-        cx<T>* t2 = t1 + (int64_t)nf * N * N * m;      // [nf][z][jy][kx]
-        {
-            KTimer tm(P, PST_K_FFTX);
-            hipLaunchKernelGGL((k_fftx_r2c_m<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
-                               P->stream, (const T*)in, t1, (const cx<T>*)P->tw, npairs, m);
-        }
+    // Mode-pruned transforms.  Workspace `tmp`: t1 = nf N N m complex ([nf][z][y][kx < m],
+    // the x-transformed lines) followed by t2 = nf N 2m m ([nf][z][jy][kx]).
+    static void modes_yz_fwd(pst_plan* P, void* out, int nf, int m, void* tmp) {
+        const int64_t m2 = 2 * m;
+        cx<T>* t1 = (cx<T>*)tmp;
+        cx<T>* t2 = t1 + (int64_t)nf * N * N * m;
         {
             KTimer tm(P, PST_K_FFTY);
             hipLaunchKernelGGL((k_fft_cols_m<T, N, false, false, true>), dim3(cdiv(m, TL), (unsigned)(nf * N)),
@@ -792,8 +788,8 @@ struct Impl {
                                (int64_t)N * m2 * m, m2 * m, m2 * m2 * m, m, s);
         }
     }
-    static void fft_c2r_modes(pst_plan* P, const void* in, void* out, int nf, int m, void* tmp) {
-        const int64_t npairs = (int64_t)nf * N * N / 2, m2 = 2 * m;
+    static void modes_yz_inv(pst_plan* P, const void* in, int nf, int m, void* tmp) {
+        const int64_t m2 = 2 * m;
         cx<T>* t1 = (cx<T>*)tmp;
         cx<T>* t2 = t1 + (int64_t)nf * N * N * m;
         {
@@ -808,10 +804,23 @@ struct Impl {
                                dim3(TB), 0, P->stream, t2, t1, (const cx<T>*)P->tw, (int64_t)m, (int64_t)m, m2 * m,
                                (int64_t)m, (int64_t)N * m, m, T(1));
         }
+    }
+    static void fft_r2c_modes(pst_plan* P, const void* in, void* out, int nf, int m, void* tmp) {
+        const int64_t npairs = (int64_t)nf * N * N / 2;
+        {
+            KTimer tm(P, PST_K_FFTX);
+            hipLaunchKernelGGL((k_fftx_r2c_m<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                               P->stream, (const T*)in, (cx<T>*)tmp, (const cx<T>*)P->tw, npairs, m);
+        }
+        modes_yz_fwd(P, out, nf, m, tmp);
+    }
+    static void fft_c2r_modes(pst_plan* P, const void* in, void* out, int nf, int m, void* tmp) {
+        const int64_t npairs = (int64_t)nf * N * N / 2;
+        modes_yz_inv(P, in, nf, m, tmp);
         {
             KTimer tm(P, PST_K_FFTX);
             hipLaunchKernelGGL((k_fftx_c2r_m<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
-                               P->stream, t1, (T*)out, (const cx<T>*)P->tw, npairs, m);
+                               P->stream, (const cx<T>*)tmp, (T*)out, (const cx<T>*)P->tw, npairs, m);
         }
     }
 
@@ -830,6 +839,8 @@ struct Impl {
             l.fft_c2r = &fft_c2r;
             l.fft_r2c_modes = &fft_r2c_modes;
             l.fft_c2r_modes = &fft_c2r_modes;
+            l.modes_yz_fwd = &modes_yz_fwd;
+            l.modes_yz_inv = &modes_yz_inv;
             return l;
         }();
         return &L;

@@ -101,6 +101,10 @@ struct Launchers {
     // compact spectra [nf][2m][2m][m]; workspace nf n n m + nf n 2m m complex
     void (*fft_r2c_modes)(pst_plan*, const void* in, void* out, int nf, int m, void* tmp);
     void (*fft_c2r_modes)(pst_plan*, const void* in, void* out, int nf, int m, void* tmp);
+    // their y and z passes alone: from / to the x-transformed lines held in the
+    // first nf n n m complex of the workspace
+    void (*modes_yz_fwd)(pst_plan*, void* out, int nf, int m, void* tmp);
+    void (*modes_yz_inv)(pst_plan*, const void* in, int nf, int m, void* tmp);
 };
 
 const Launchers* launchers_for(int n, int precision);

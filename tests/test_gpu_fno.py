@@ -86,6 +86,53 @@ def test_adam_reduces_loss(P, torch, case, mfma):
     assert losses[-1] < 0.9 * losses[0] and all(np.diff(losses) < 0.02 * losses[0])
 
 
+# Shapes that exercise the inference kernels' edge cases: an odd radix (24),
+# odd channel counts (an unpaired last line), more than 32 channels or hidden
+# units (several matrix tiles, masked rows), one row per block (96, 128) and a
+# single layer (lift straight into the projection).
+SHAPES = [
+    dict(n=24, width=5, modes=4, layers=2, hidden=40),
+    dict(n=48, width=36, modes=5, layers=1, hidden=16),
+    dict(n=96, width=3, modes=6, layers=2, hidden=8),
+    dict(n=128, width=2, modes=4, layers=1, hidden=8),
+]
+
+
+_shape_cache = {}
+
+
+def shape_case(i):
+    if i not in _shape_cache:
+        import oracle.fno as F
+        cfg = SHAPES[i]
+        theta = I.fno_init_params(seed=11, out_scale=0.5, **cfg).astype(np.float32).astype(np.float64)
+        n, nb = cfg["n"], 2 if cfg["n"] <= 48 else 1
+        rng = np.random.default_rng(12)
+        u = rng.standard_normal((nb, 3, n, n, n)).astype(np.float32).astype(np.float64)
+        _shape_cache[i] = (theta, u, F.forward(theta, u, cfg) - u)
+    return _shape_cache[i]
+
+
+@pytest.mark.parametrize("mfma,tf", [(False, 1e-5), (True, 2e-2)])
+@pytest.mark.parametrize("i", range(len(SHAPES)),
+                         ids=[f"n{c['n']}w{c['width']}l{c['layers']}h{c['hidden']}" for c in SHAPES])
+def test_forward_shapes(P, torch, i, mfma, tf):
+    cfg = SHAPES[i]
+    theta, u, y_ref = shape_case(i)
+    nb = u.shape[0]
+    fno = P.FNO(batch=nb, mfma=mfma, **cfg)
+    fno.set_params(theta)
+    ud = torch.from_numpy(u).float().cuda()
+    od = torch.empty_like(ud)
+    fno.forward(ud, od)
+    y = od.cpu().numpy() - u
+    for b in range(nb):
+        assert rel(y[b], y_ref[b]) < tf, b
+    # in place (out aliases u) gives the same result
+    fno.forward(ud, ud)
+    assert np.array_equal(ud.cpu().numpy(), od.cpu().numpy())
+
+
 def test_adam_matches_formula(P, torch, case):
     """One Adam step from zero moments moves every parameter by lr * g / (|g| + eps')."""
     theta, u, tgt, *_ = case
