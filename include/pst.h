@@ -271,7 +271,8 @@ typedef struct {
     int modes;   /* m: retained modes per direction (2 m <= n) */
     int layers;  /* spectral layers (1..8) */
     int hidden;  /* h: projection hidden width (1..256) */
-    int batch;   /* maximum batch (1..64); buffers are sized for it */
+    int batch;   /* maximum batch (1..64, and 2 batch width + width^2 <= 8192 so a
+                    mode's spectral mixing fits in 64 KB of LDS); buffers are sized for it */
     int mfma;    /* 1: BF16 matrix-core channel mixing; 0: FP32 */
 } pst_fno_params;
 

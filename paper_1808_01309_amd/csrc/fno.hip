@@ -182,31 +182,48 @@ __global__ __launch_bounds__(GT) void k_bgrad(const float* __restrict__ Y, int O
     if (threadIdx.x == 0) grad[o] = (float)sh[0];
 }
 
-// forward spectral mixing, one block per retained mode
+// forward spectral mixing on compact spectra [b][c][mode] (mode stride 1,
+// channel stride nm): out[b][o][m] = sum_c R[m][c][o] V[b][c][m].  A block
+// takes MB consecutive modes so that every (b, c) row is read and written as
+// one contiguous MB-element segment; the modes' slices meet in LDS, and each
+// mode's weight matrix is staged there (coalesced) before it is used.
+//   LDS: Vh [MB][B C], Out [MB][B O], Rs [C][O]
 __global__ __launch_bounds__(GT) void k_mix_fwd(const cx<float>* __restrict__ spec_in, const cx<float>* __restrict__ R,
-                                                const int* __restrict__ modeoff, int64_t fsz, int B, int C, int O,
-                                                cx<float>* __restrict__ spec_out, cx<float>* __restrict__ vstore) {
+                                                int nm, int MB, int B, int C, int O, cx<float>* __restrict__ spec_out,
+                                                cx<float>* __restrict__ vstore) {
     extern __shared__ cx<float> shm[];
-    cx<float>* Vh = shm;            // [B][C]
-    cx<float>* Rm = shm + B * C;    // [C][O]
-    const int m = blockIdx.x;
-    const int64_t off = modeoff[m];
-    for (int i = threadIdx.x; i < B * C; i += GT) {
-        const cx<float> v = spec_in[(int64_t)i * fsz + off];
-        Vh[i] = v;
-        if (vstore) vstore[(int64_t)m * B * C + i] = v;
+    cx<float>* Vh = shm;
+    cx<float>* Out = Vh + MB * B * C;
+    cx<float>* Rs = Out + MB * B * O;
+    const int m0 = blockIdx.x * MB;
+    const int mb = nm - m0 < MB ? nm - m0 : MB;
+    for (int q = threadIdx.x; q < B * C * MB; q += GT) {
+        const int i = q / MB, mm = q % MB;
+        if (mm >= mb) continue;
+        const cx<float> v = spec_in[(int64_t)i * nm + m0 + mm];
+        Vh[mm * B * C + i] = v;
+        if (vstore) vstore[(int64_t)(m0 + mm) * B * C + i] = v;
     }
-    for (int i = threadIdx.x; i < C * O; i += GT) Rm[i] = R[(int64_t)m * C * O + i];
-    __syncthreads();
-    for (int i = threadIdx.x; i < B * O; i += GT) {
-        const int b = i / O, o = i % O;
-        float re = 0.f, im = 0.f;
-        for (int c = 0; c < C; ++c) {
-            const cx<float> r = Rm[c * O + o], v = Vh[b * C + c];
-            re += r.x * v.x - r.y * v.y;
-            im += r.x * v.y + r.y * v.x;
+    for (int mm = 0; mm < mb; ++mm) {
+        const cx<float>* Rm = R + (int64_t)(m0 + mm) * C * O;
+        for (int j = threadIdx.x; j < C * O; j += GT) Rs[j] = Rm[j];
+        __syncthreads();
+        const cx<float>* V = Vh + mm * B * C;
+        for (int i = threadIdx.x; i < B * O; i += GT) {
+            const int b = i / O, o = i % O;
+            float re = 0.f, im = 0.f;
+            for (int c = 0; c < C; ++c) {
+                const cx<float> r = Rs[c * O + o], v = V[b * C + c];
+                re += r.x * v.x - r.y * v.y;
+                im += r.x * v.y + r.y * v.x;
+            }
+            Out[mm * B * O + i] = {re, im};
         }
-        spec_out[(int64_t)i * fsz + off] = {re, im};
+        __syncthreads();  // Rs is rewritten by the next mode
+    }
+    for (int q = threadIdx.x; q < B * O * MB; q += GT) {
+        const int i = q / MB, mm = q % MB;
+        if (mm < mb) spec_out[(int64_t)i * nm + m0 + mm] = Out[mm * B * O + i];
     }
 }
 
@@ -420,6 +437,8 @@ extern "C" pst_status pst_fno_create(const pst_fno_params* p, void* hip_stream, 
     if (p->width < 1 || p->width > 64 || p->modes < 1 || 2 * p->modes > p->n || p->layers < 1 || p->layers > 8 ||
         p->hidden < 1 || p->hidden > 256 || p->batch < 1 || p->batch > 64)
         return ffail(nullptr, PST_ERR_INVALID_ARG, "width 1..64, 1 <= modes <= n/2, layers 1..8, hidden 1..256, batch 1..64");
+    if (2 * p->batch * p->width + p->width * p->width > 8192)
+        return ffail(nullptr, PST_ERR_INVALID_ARG, "2 batch width + width^2 must not exceed 8192 (spectral mixing LDS)");
     if ((long)p->n * p->n * p->n % 32 != 0) return ffail(nullptr, PST_ERR_UNSUPPORTED_N, "n^3 must be a multiple of 32");
     pst_fno* F = new pst_fno();
     F->p = *p;
@@ -585,6 +604,17 @@ static void dense_grad(pst_fno* F, const FnoDense& d, const float* Y, const floa
     hipLaunchKernelGGL(k_bgrad, dim3(d.O), dim3(GT), 0, F->stream, Y, d.O, F->P, B, F->grad + d.off + (int64_t)d.O * d.K);
 }
 
+// forward spectral mixing launch: MB modes per block, LDS (2 MB B W + W W
+// complex) <= 64 KB for every admissible batch and width
+static void mix_fwd(pst_fno* F, int l, int B, cx<float>* vstore) {
+    const int W = F->p.width;
+    int MB = 2048 / (B * W);
+    MB = MB < 1 ? 1 : (MB > 8 ? 8 : MB);
+    const size_t sh = sizeof(cx<float>) * (2 * (size_t)MB * B * W + (size_t)W * W);
+    hipLaunchKernelGGL(k_mix_fwd, dim3((F->nm + MB - 1) / MB), dim3(GT), sh, F->stream, F->specA,
+                       (const cx<float>*)(F->theta + F->offR[l]), F->nm, MB, B, W, W, F->specB, vstore);
+}
+
 static void forward_pass(pst_fno* F, const float* u, int B, float* out) {
     const int W = F->p.width, L = F->p.layers;
     const int64_t act = (int64_t)B * W * F->P;
@@ -599,10 +629,7 @@ static void forward_pass(pst_fno* F, const float* u, int B, float* out) {
         float* sl = F->s + l * astride;
         // spectral branch: kb = c2r(R . r2c(v))
         F->fft->L->fft_r2c_modes(F->fft, vl, F->specA, B * W, F->p.modes, F->ffttmp);
-        const size_t sh = sizeof(cx<float>) * ((size_t)B * W + (size_t)W * W);
-        hipLaunchKernelGGL(k_mix_fwd, dim3(F->nm), dim3(GT), sh, F->stream, F->specA,
-                           (const cx<float>*)(F->theta + F->offR[l]), F->modeoff, F->fsz, B, W, W, F->specB,
-                           F->vst + (int64_t)l * F->nm * F->p.batch * W);
+        mix_fwd(F, l, B, F->vst + (int64_t)l * F->nm * F->p.batch * W);
         F->fft->L->fft_c2r_modes(F->fft, F->specB, F->kb, B * W, F->p.modes, F->ffttmp);
         const FnoDense& d = F->wc[l];
         const float* bias = F->theta + d.off + d.O * d.K;
@@ -625,12 +652,9 @@ static void forward_fused(pst_fno* F, const float* u, int B, float* out) {
     const int64_t astride = (int64_t)F->p.batch * W * F->P;
     void* act[2] = {F->v, F->v + astride};
     fno_fused_lift(F, u, B, act[0], F->ffttmp);
-    const size_t sh = sizeof(cx<float>) * ((size_t)B * W + (size_t)W * W);
     for (int l = 0; l < L; ++l) {
         F->fft->L->modes_yz_fwd(F->fft, F->specA, B * W, m, F->ffttmp);
-        hipLaunchKernelGGL(k_mix_fwd, dim3(F->nm), dim3(GT), sh, F->stream, F->specA,
-                           (const cx<float>*)(F->theta + F->offR[l]), F->modeoff, F->fsz, B, W, W, F->specB,
-                           (cx<float>*)nullptr);
+        mix_fwd(F, l, B, nullptr);
         F->fft->L->modes_yz_inv(F->fft, F->specB, B * W, m, F->ffttmp);
         if (l < L - 1) fno_fused_layer(F, l, B, act[l & 1], act[(l + 1) & 1], F->ffttmp);
         else fno_fused_last(F, l, B, act[l & 1], F->ffttmp, u, out);

@@ -45,7 +45,7 @@ template <int N> size_t fused_lds(int W) {
 }
 
 // Block geometry: blockIdx.x = (b N + z) (N / RB) + yb, first point p0 of the
-// block in a field, lines l = r W + c (row r, channel c) live at X[c][r N + x].
+// block in a field; the block's lines (row r, channel c) live at X[c][r N + x].
 struct RowBlock {
     int b, z, y0;
     int64_t p0;
@@ -60,9 +60,16 @@ template <int N> __device__ __forceinline__ RowBlock row_block() {
     r.p0 = ((int64_t)r.z * N + r.y0) * N;
     return r;
 }
+// Line l of a block is row r = l % RB of channel c = l / RB: the two lines of a
+// pair are adjacent rows of one channel (RB even), whose t1 segments are contiguous.
 template <int N> __device__ __forceinline__ int64_t t1_line(const RowBlock& rb, int W, int m, int l) {
-    const int r = l / W, c = l % W;
+    constexpr int RB = fno_rows<N>();
+    const int r = l % RB, c = l / RB;
     return ((((int64_t)rb.b * W + c) * N + rb.z) * N + rb.y0 + r) * m;
+}
+template <int N> __device__ __forceinline__ int x_line(int l) {
+    constexpr int RB = fno_rows<N>();
+    return (l / RB) * RB * N + (l % RB) * N;  // X[c][r N + x]
 }
 
 // x r2c of the block's RB W lines held in X, keeping kx < m, into t1.
@@ -79,8 +86,8 @@ __device__ __forceinline__ void rows_r2c(const float* X, int W, int m, const Row
     for (int base = 0; base < npair; base += NPG) {  // same trip count in every thread
         const int l0 = 2 * (base + li), l1 = l0 + 1;
         const bool a0 = l0 < NL, a1 = l1 < NL;
-        const float* x0 = X + (a0 ? (l0 % W) * PB + (l0 / W) * N : 0);
-        const float* x1 = X + (a1 ? (l1 % W) * PB + (l1 / W) * N : 0);
+        const float* x0 = X + (a0 ? x_line<N>(l0) : 0);
+        const float* x1 = X + (a1 ? x_line<N>(l1) : 0);
         cx<float> v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -133,8 +140,8 @@ __device__ __forceinline__ void rows_c2r(const cx<float>* __restrict__ t1, int W
             else v[e] = {A.x + B.y, B.x - A.y};  // zero when k < 0
         }
         F::run(v, g, lds, tw);
-        float* x0 = X + (a0 ? (l0 % W) * PB + (l0 / W) * N : 0);
-        float* x1 = X + (a1 ? (l1 % W) * PB + (l1 / W) * N : 0);
+        float* x0 = X + (a0 ? x_line<N>(l0) : 0);
+        float* x1 = X + (a1 ? x_line<N>(l1) : 0);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int q = F::last_pos(g, e);
@@ -146,37 +153,53 @@ __device__ __forceinline__ void rows_c2r(const cx<float>* __restrict__ t1, int W
     }
 }
 
-// acc[r] = sum_k W[ot 32 + m(r)][k] x[k][n] over k < K for this lane's point n,
-// the MFMA 32x32x8 register layout: m(r) = 8 (r / 4) + 4 kg + r % 4.
-// x comes from a column of a channel-major array (element stride xs).
-template <bool MFMA, typename XT>
-__device__ __forceinline__ f32x16 mix_tile(const unsigned short* __restrict__ Wb, const float* __restrict__ Wf,
-                                           int Kpad, int K, int ot, const XT* x, int64_t xs, int n, int kg) {
+// Channel mixing of one tile: acc[r] = sum_k W[ot 32 + m(r)][k] x[k][n] over
+// k < K for this lane's point n, in the MFMA 32x32x8 register layout
+// m(r) = 8 (r / 4) + 4 kg + r % 4.  x is a column of a channel-major array
+// (element stride xs).  K <= 64: at most 8 MFMA steps.
+constexpr int KS_MAX = 8;
+struct BOps {
+    bf16x4 b[KS_MAX];
+};
+template <typename XT>
+__device__ __forceinline__ void load_bops(BOps& o, const XT* x, int64_t xs, int K, int Kpad, int kg) {
+#pragma unroll
+    for (int s = 0; s < KS_MAX; ++s) {
+        if (s >= Kpad / 8) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 8 * s + 4 * kg + j;
+            if constexpr (sizeof(XT) == 2) o.b[s][j] = k < K ? (short)x[k * xs] : (short)0;
+            else o.b[s][j] = k < K ? (short)f2bf(x[k * xs]) : (short)0;
+        }
+    }
+}
+__device__ __forceinline__ f32x16 mfma_tile(const BOps& o, const unsigned short* __restrict__ Wb, int Kpad, int ot,
+                                            int n, int kg) {
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    if constexpr (MFMA) {
-        const unsigned short* wrow = Wb + (int64_t)(ot * 32 + n) * Kpad + 4 * kg;
-        for (int s = 0; s < Kpad / 8; ++s) {
-            bf16x4 aa, bb;
+    const unsigned short* wrow = Wb + (int64_t)(ot * 32 + n) * Kpad + 4 * kg;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = 8 * s + 4 * kg + j;
-                if constexpr (sizeof(XT) == 2) bb[j] = k < K ? (short)x[k * xs] : (short)0;
-                else bb[j] = k < K ? (short)f2bf(x[k * xs]) : (short)0;
-                aa[j] = (short)wrow[8 * s + j];
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aa, bb, acc, 0, 0, 0);
-        }
-    } else {
-        for (int k = 0; k < K; ++k) {
-            const float xv = (float)x[k * xs];
+    for (int s = 0; s < KS_MAX; ++s) {
+        if (s >= Kpad / 8) break;
+        bf16x4 aa;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int mm = 8 * (r / 4) + 4 * kg + (r % 4);
-                acc[r] += Wf[(int64_t)(ot * 32 + mm) * Kpad + k] * xv;
-            }
-        }
+        for (int j = 0; j < 4; ++j) aa[j] = (short)wrow[8 * s + j];
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aa, o.b[s], acc, 0, 0, 0);
+    }
+    return acc;
+}
+// FP32 FMA variant, same register layout (W FP32 [.][Kpad])
+__device__ __forceinline__ f32x16 fma_tile(const float* __restrict__ Wf, int Kpad, int K, int ot, const float* x,
+                                           int64_t xs, int kg) {
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int k = 0; k < K; ++k) {
+        const float xv = x[k * xs];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[r] += Wf[(int64_t)(ot * 32 + 8 * (r / 4) + 4 * kg + (r % 4)) * Kpad + k] * xv;
     }
     return acc;
 }
@@ -219,20 +242,37 @@ __global__ __launch_bounds__(FT) void k_fno_layer(const typename Act<BF>::T* __r
                                                   const cx<float>* __restrict__ tw, ProjArgs pa) {
     constexpr int PB = fno_rows<N>() * N, PT = PB / 32;
     constexpr int64_t P3 = (int64_t)N * N * N;
+    static_assert(sizeof(float) * 4 * 256 <= sizeof(cx<float>) * (FT / NCfg<N>::G) * LineLds<float>::size(N),
+                  "projection weights (hidden <= 256) must fit in the FFT scratch");
     extern __shared__ float X[];
     cx<float>* fl = (cx<float>*)(X + W * PB);
     const RowBlock rb = row_block<N>();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 31, kg = lane >> 5;
 
+    const typename Act<BF>::T* vb = vin + (int64_t)rb.b * W * P3 + rb.p0 + n;
+    const int ntile = (Opad / 32) * PT;
+
+
     // spectral branch of every line of the block
     rows_c2r<N>(t1, W, m, rb, X, tw, fl);
     __syncthreads();
+    float* wl = (float*)fl;  // last layer: [bq1; Wq2] (4 H floats) in the now unused FFT scratch
+    if constexpr (LAST) {
+        for (int i = threadIdx.x; i < 4 * pa.H; i += FT)
+            wl[i] = i < pa.H ? pa.bq1[i] : pa.Wq2[i - pa.H];
+    }
 
     // channel mixing + bias + spectral branch (+ GELU), tiles of 32 channels x 32 points
-    const int ntile = (Opad / 32) * PT;
     for (int t = wave; t < ntile; t += FT / 64) {
         const int ot = t / PT, pt0 = (t % PT) * 32;
-        const f32x16 acc = mix_tile<BF>(Wb, Wf, Kpad, W, ot, vin + (int64_t)rb.b * W * P3 + rb.p0 + pt0 + n, P3, n, kg);
+        f32x16 acc;
+        if constexpr (BF) {
+            BOps ops;
+            load_bops(ops, vb + pt0, P3, W, Kpad, kg);
+            acc = mfma_tile(ops, Wb, Kpad, ot, n, kg);
+        } else {
+            acc = fma_tile(Wf, Kpad, W, ot, vb + pt0, P3, kg);
+        }
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int o = ot * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
@@ -251,20 +291,28 @@ __global__ __launch_bounds__(FT) void k_fno_layer(const typename Act<BF>::T* __r
     if constexpr (!LAST) {
         rows_r2c<N>(X, W, m, rb, t1, tw, fl);
     } else {
-        // projection: out = u + Wq2 gelu(Wq1 v + bq1) + bq2, one 32-point tile per wave
+        // projection out = u + Wq2 gelu(Wq1 v + bq1) + bq2, one 32-point tile
+        // per wave; bq1 and Wq2 were staged in LDS (the FFT scratch).
         for (int t = wave; t < PT; t += FT / 64) {
             const int pt0 = t * 32;
             float y0 = 0.f, y1 = 0.f, y2 = 0.f;
             for (int ht = 0; ht < pa.Hpad / 32; ++ht) {
-                const f32x16 acc = mix_tile<BF>(pa.Wb, pa.Wf, pa.Kpad, W, ht, X + pt0 + n, (int64_t)PB, n, kg);
+                f32x16 acc;
+                if constexpr (BF) {
+                    BOps ops;
+                    load_bops(ops, X + pt0 + n, (int64_t)PB, W, pa.Kpad, kg);
+                    acc = mfma_tile(ops, pa.Wb, pa.Kpad, ht, n, kg);
+                } else {
+                    acc = fma_tile(pa.Wf, pa.Kpad, W, ht, X + pt0 + n, (int64_t)PB, kg);
+                }
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int h = ht * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
                     if (h >= pa.H) continue;
-                    const float a = gelu_f(acc[r] + pa.bq1[h]);
-                    y0 += pa.Wq2[h] * a;
-                    y1 += pa.Wq2[pa.H + h] * a;
-                    y2 += pa.Wq2[2 * pa.H + h] * a;
+                    const float a = gelu_f(acc[r] + wl[h]);
+                    y0 += wl[pa.H + h] * a;
+                    y1 += wl[2 * pa.H + h] * a;
+                    y2 += wl[3 * pa.H + h] * a;
                 }
             }
             // the two half-waves hold disjoint hidden units of the same points

@@ -146,3 +146,14 @@ def test_adam_matches_formula(P, torch, case):
     th1 = fno.get_params().astype(np.float64)
     ref = theta - 1e-3 * g / (np.abs(g) + 1e-8)
     assert np.abs(th1 - ref).max() < 1e-6
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=16, width=8, modes=9, layers=2, hidden=16, batch=2),     # 2 m > n
+    dict(n=40, width=8, modes=3, layers=2, hidden=16, batch=2),     # unsupported n
+    dict(n=64, width=64, modes=12, layers=1, hidden=8, batch=64),   # mixing LDS bound
+    dict(n=16, width=8, modes=3, layers=9, hidden=16, batch=2),     # too many layers
+])
+def test_invalid_configs(P, torch, bad):
+    with pytest.raises(P.PstError):
+        P.FNO(**bad)
