@@ -172,10 +172,26 @@ struct TileLds {
     __device__ __forceinline__ cx<T>& operator()(int i) const { return p[i * TLP]; }
 };
 
+// Synchronisation of the LDS exchanges between transform stages: the whole
+// workgroup, or (WS) only the wavefront, when the G threads of every line are
+// lanes of one wavefront.  LDS operations of one wavefront complete in program
+// order, so a wavefront-scope fence that keeps the compiler from moving LDS
+// accesses across it is enough there.
+template <bool WS>
+__device__ __forceinline__ void lds_sync() {
+    if constexpr (WS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // One n-point transform of one line; the caller has loaded v[e] = x[first_pos(g, e)]
-// and receives v[e] = X[last_pos(g, e)].  Every thread of the block must call it
-// (it contains __syncthreads).
-template <typename T, class P, int G, bool INV, bool REV = false>
+// and receives v[e] = X[last_pos(g, e)].  Every thread of the block (WS: of the
+// wavefront) must call it: it synchronises between stages with lds_sync<WS>.
+template <typename T, class P, int G, bool INV, bool REV = false, bool WS = false>
 struct Fft {
     static constexpr int N = P::N;
     static constexpr int S = P::S;
@@ -183,6 +199,7 @@ struct Fft {
     static constexpr int R_FIRST = radix_at<P, REV>(0);
     static constexpr int R_LAST = radix_at<P, REV>(S - 1);
     static_assert(N % G == 0, "threads per line must divide n");
+    static_assert(!WS || 64 % G == 0, "wavefront sync needs the lines inside wavefronts");
 
     __device__ __forceinline__ static int first_pos(int g, int e) {
         return g + (e / R_FIRST) * G + (e % R_FIRST) * (N / R_FIRST);
@@ -221,12 +238,12 @@ struct Fft {
 #pragma unroll
                 for (int r = 0; r < R; ++r) lds(base + r * NS) = v[i * R + r];
             }
-            __syncthreads();
+            lds_sync<WS>();
 #pragma unroll
             for (int i = 0; i < NB2; ++i)
 #pragma unroll
                 for (int r = 0; r < R2; ++r) v[i * R2 + r] = lds(g + i * G + r * (N / R2));
-            __syncthreads();
+            lds_sync<WS>();
             stage<s + 1>(v, g, lds, tw);
         }
     }

@@ -95,7 +95,10 @@ __device__ __forceinline__ void zinv_body(const cx<T>* __restrict__ st, cx<T>* _
                                           const cx<T>* __restrict__ tw, const Geo& geo, int64_t unit, int tid,
                                           cx<T>* sm) {
     constexpr int N = CF::N, G = CF::G;
-    using F = Fft<T, typename CF::P, G, true>;
+    // A line's G threads are lanes of one wavefront: the FP64 transforms
+    // synchronise per wavefront (measured faster there; FP32 keeps the
+    // workgroup barrier, which measured slightly faster for it).
+    using F = Fft<T, typename CF::P, G, true, false, sizeof(T) == 8>;
     constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
     const int l = tid / G, g = tid % G;
     const int64_t line = unit * LPB + l;
