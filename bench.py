@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-fft", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-fno", action="store_true")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="run the whole surrogate pipeline (data, ~70 s of training, evaluation, timed "
+                         "hybrid rollout) instead of reporting its committed summary")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counter scaling)")
     return ap.parse_args()
@@ -188,6 +192,54 @@ def cpu_baseline(n):
                       f"{n}^3 took {dt:.2f} s; x4 stages per RK4 step (stage updates excluded)"}
 
 
+FNO_CFG = dict(n=64, width=32, modes=12, layers=4, hidden=128)
+
+
+def run_fno(pst, torch, I, batch=8, reps=20, train_reps=5):
+    """FNO surrogate at 64^3 (4 spectral layers, 12 modes, width 32, hidden 128,
+    BF16 matrix-core channel mixing), batch 8, seeded random weights and
+    inputs: forward (fused inference kernels) and one training step (forward,
+    loss, backward, Adam)."""
+    fno = pst.FNO(batch=batch, mfma=True, **FNO_CFG)
+    fno.set_params(I.fno_init_params(seed=1, out_scale=0.5, **FNO_CFG).astype(np.float32))
+    n = FNO_CFG["n"]
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    u = torch.randn((batch, 3, n, n, n), device="cuda", generator=gen)
+    tgt = u + 0.1 * torch.randn((batch, 3, n, n, n), device="cuda", generator=gen)
+    out = torch.empty_like(u)
+    for _ in range(3):
+        fno.forward(u, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fno.forward(u, out)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) * 1e3 / reps
+    fno.train_step(u, tgt, 1e-5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(train_reps):
+        fno.train_step(u, tgt, 1e-5)
+    torch.cuda.synchronize()
+    trn = (time.perf_counter() - t0) * 1e3 / train_reps
+    fno.close()
+    return {"config": dict(FNO_CFG, batch=batch, mfma=True), "forward_ms": fwd, "train_step_ms": trn}
+
+
+def surrogate_summary(live):
+    """Surrogate speed-up: the pipeline run live, or the committed summary of its
+    last full run (which trains for about 70 s)."""
+    if live:
+        from paper_1808_01309_amd import run_surrogate
+        res = run_surrogate.run([])
+        return dict(res["summary"], source="live run (python -m paper_1808_01309_amd.run_surrogate)")
+    path = os.path.join(ROOT, "profiles", "surrogate_c5_fno64.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    return dict(rec["summary"], source="profiles/surrogate_c5_fno64.json (not re-measured in this run)")
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -238,6 +290,10 @@ def main():
     if not a.no_ensemble:
         print("[bench] ensemble: 96 runs (48^3, 64^3, 96^3), 200 RK4 steps", file=sys.stderr, flush=True)
         out_extra["ensemble"] = run_ensemble(pst, torch, I)
+    if not a.no_fno:
+        print("[bench] FNO surrogate forward / training step (64^3, batch 8)", file=sys.stderr, flush=True)
+        out_extra["fno"] = run_fno(pst, torch, I)
+    out_extra["surrogate"] = surrogate_summary(a.surrogate)
     # dominant kernel of the headline (FP32) step
     dom = max(KINDS, key=lambda k: tm32[k][0])
     ach = kb32[dom] / per32[dom] / 1e6

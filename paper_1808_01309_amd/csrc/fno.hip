@@ -156,7 +156,8 @@ __global__ void k_wgrad_reduce(const float* __restrict__ partial, int nblk, int 
                                float* __restrict__ grad) {
     const int t = blockIdx.x;
     const int ot = t / ktiles, kt = t % ktiles;
-    for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
+    // one thread per tile element (blockIdx.y selects 64 of the 1024)
+    for (int i = blockIdx.y * blockDim.x + threadIdx.x; i < 1024; i += gridDim.y * blockDim.x) {
         const int m = i / 32, nn = i % 32;
         const int o = ot * 32 + m, k = kt * 32 + nn;
         if (o >= O || k >= K) continue;
@@ -166,20 +167,35 @@ __global__ void k_wgrad_reduce(const float* __restrict__ partial, int nblk, int 
     }
 }
 
-// db[o] = sum_{b,p} Y[b][o][p] (one block per channel, fixed-order tree)
-__global__ __launch_bounds__(GT) void k_bgrad(const float* __restrict__ Y, int O, int P, int B, float* __restrict__ grad) {
+// db[o] = sum_{b,p} Y[b][o][p] in two fixed-order levels: block (o, c) sums
+// the point range c of every batch item (FP64, tree over the block), then one
+// thread per channel adds the BG_CHUNKS partials in order.
+constexpr int BG_CHUNKS = 64;
+__global__ __launch_bounds__(GT) void k_bgrad_part(const float* __restrict__ Y, int O, int P, int B,
+                                                   double* __restrict__ part) {
     __shared__ double sh[GT];
-    const int o = blockIdx.x;
+    const int o = blockIdx.x, c = blockIdx.y;
+    const int len = (P + BG_CHUNKS - 1) / BG_CHUNKS;
+    const int p0 = c * len, p1 = p0 + len < P ? p0 + len : P;
     double s = 0.0;
-    for (int b = 0; b < B; ++b)
-        for (int p = threadIdx.x; p < P; p += GT) s += Y[((int64_t)b * O + o) * P + p];
+    for (int b = 0; b < B; ++b) {
+        const float* y = Y + ((int64_t)b * O + o) * P;
+        for (int p = p0 + threadIdx.x; p < p1; p += GT) s += y[p];
+    }
     sh[threadIdx.x] = s;
     __syncthreads();
     for (int w = GT / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) grad[o] = (float)sh[0];
+    if (threadIdx.x == 0) part[o * BG_CHUNKS + c] = sh[0];
+}
+__global__ void k_bgrad_reduce(const double* __restrict__ part, int O, float* __restrict__ grad) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= O) return;
+    double s = 0.0;
+    for (int c = 0; c < BG_CHUNKS; ++c) s += part[o * BG_CHUNKS + c];
+    grad[o] = (float)s;
 }
 
 // forward spectral mixing on compact spectra [b][c][mode] (mode stride 1,
@@ -599,9 +615,12 @@ static void dense_grad(pst_fno* F, const FnoDense& d, const float* Y, const floa
         hipLaunchKernelGGL((k_wgrad<false, true>), grid, dim3(GT), 0, F->stream, Y, d.O, X, d.K, F->P, total, ppb, ktiles, F->part);
     else
         hipLaunchKernelGGL((k_wgrad<false, false>), grid, dim3(GT), 0, F->stream, Y, d.O, X, d.K, F->P, total, ppb, ktiles, F->part);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(ntiles), dim3(256), 0, F->stream, F->part, nblk, ntiles, ktiles, d.O, d.K,
-                       F->grad + d.off);
-    hipLaunchKernelGGL(k_bgrad, dim3(d.O), dim3(GT), 0, F->stream, Y, d.O, F->P, B, F->grad + d.off + (int64_t)d.O * d.K);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(ntiles, 16), dim3(64), 0, F->stream, F->part, nblk, ntiles, ktiles, d.O,
+                       d.K, F->grad + d.off);
+    // bias partials in F->lpart (its loss partials were read back before the backward pass)
+    hipLaunchKernelGGL(k_bgrad_part, dim3(d.O, BG_CHUNKS), dim3(GT), 0, F->stream, Y, d.O, F->P, B, F->lpart);
+    hipLaunchKernelGGL(k_bgrad_reduce, dim3((d.O + 255) / 256), dim3(256), 0, F->stream, F->lpart, d.O,
+                       F->grad + d.off + (int64_t)d.O * d.K);
 }
 
 // forward spectral mixing launch: MB modes per block, LDS (2 MB B W + W W

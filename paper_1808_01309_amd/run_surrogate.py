@@ -23,7 +23,8 @@ import time
 import numpy as np
 
 
-def main(argv=None):
+def run(argv=None):
+    """Runs the pipeline; returns the result dictionary."""
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--seeds", type=int, default=40)
@@ -82,7 +83,22 @@ def main(argv=None):
     res["windows"] = S.window_errors(fno, x0, apps=a.apps)
     log("hybrid rollout")
     res["hybrid"] = S.rollout(fno, x0, apps=a.apps)
-    print(json.dumps(res))
+    h = res["hybrid"]
+    res["summary"] = {
+        "speedup": h.get("speedup"),
+        "fno_forward_ms_batch": res["fno_forward_ms_batch"],
+        "max_audited_window_err": max(h["audit_err"]) if h["audit_err"] else None,
+        "accepted_windows": h["apps"] - h["solver_windows"] - h["audit_fail"] - h["guard_fail"],
+        "solver_windows": h["solver_windows"], "audit_fail": h["audit_fail"], "guard_fail": h["guard_fail"],
+        "max_one_application_err": max(res["windows"]["one_step_err"]),
+        "final_rel_l2_vs_plain_max": max(h["final_rel_l2"]) if "final_rel_l2" in h else None,
+    }
+    fno.close()
+    return res
+
+
+def main(argv=None):
+    print(json.dumps(run(argv)))
 
 
 if __name__ == "__main__":
