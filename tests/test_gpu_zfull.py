@@ -1,0 +1,188 @@
+"""Parity at the full workload sizes, in the launch configurations the
+benchmark times (collected after the other GPU tests: these are the slow ones).
+
+* Navier-Stokes 512^3, RK4, dt = 5e-4, nu = 2e-3, shell forcing: one right-hand
+  side and one RK4 step of the FP32 and FP64 paths against the FP64 oracle,
+  every coefficient (the oracle needs seconds per right-hand side on the host
+  cores).
+* MHD 1024^3, RK2, dt = 2.5e-4, nu = eta = 1e-3, FP32: properties that hold at
+  any size (the oracle would need ~100 GB of host memory there).  The
+  dealiased nonlinear terms conserve total energy and cross-helicity exactly,
+  so their transfers must vanish to rounding; over 5 steps the total energy
+  must fall by the dissipation alone.
+* The 96-run ensemble (32 x 48^3, 48 x 64^3, 16 x 96^3) with its autotuned
+  schedule: the graph-replayed persistent step equals the batched launches
+  bitwise for every run, and one run of each size equals the oracle.
+* The FNO at 64^3 (width 32, 12 modes, 4 layers, hidden 128) created for
+  batch 8: the last sample's output against the FP64 oracle, BF16 and FP32.
+"""
+import numpy as np
+import pytest
+
+from paper_1808_01309_amd import inputs as I
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1808_01309_amd import pst
+    return pst
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+# ------------------------------------------------------------ NS 512^3
+N512, NU512, DT512 = 512, 2e-3, 5e-4
+
+
+@pytest.fixture(scope="module")
+def ns512(O):
+    u0 = I.random_solenoidal(N512, 1)
+    f = I.forcing_shells(N512, 1)
+    rhs = O.ns_rhs(u0, f)
+    step = O.step(u0, 1, dt=DT512, nu=NU512, rk=4, fhat=f)
+    return u0, f, rhs, step
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_ns512_rhs_and_step(P, torch, ns512, prec):
+    u0, f, rhs_ref, step_ref = ns512
+    plan = P.Plan(N512, precision=prec, rk_order=4, nu=NU512, dt=DT512)
+    plan.set_forcing(f)
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    sd = torch.from_numpy(u0).to(ct).cuda()
+    rd = torch.empty_like(sd)
+    plan.rhs(sd, rd)
+    got = rd.cpu().numpy()
+    assert max(rel(got[c], rhs_ref[c]) for c in range(3)) < TOL[prec]
+    del rd
+    plan.set_state(sd)
+    del sd
+    plan.step(1)
+    got = plan.get_state()
+    assert max(rel(got[c], step_ref[c]) for c in range(3)) < TOL[prec]
+    plan.close()
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------ MHD 1024^3
+N1024, KB = 1024, 24   # the E(k) ~ k^2 exp(-(k/3)^2) fields are below 1e-25 beyond |k_i| = 24
+
+
+def embed(torch, small, n, kb):
+    """Modes |k_i| <= kb of a field generated on a small grid, placed in the
+    n^3 layout (the counter-based generator gives every mode the same value
+    on any grid)."""
+    m = small.shape[1]
+    s = torch.from_numpy(small).cuda()
+    big = torch.zeros((3, n, n, n // 2 + 1), dtype=s.dtype, device="cuda")
+    for bz, sz in ((slice(0, kb + 1), slice(0, kb + 1)), (slice(n - kb, n), slice(m - kb, m))):
+        for by, sy in ((slice(0, kb + 1), slice(0, kb + 1)), (slice(n - kb, n), slice(m - kb, m))):
+            big[:, bz, by, :kb + 1] = s[:, sz, sy, :kb + 1]
+    return big
+
+
+def wsum(torch, t):
+    """sum over a half spectrum with weight 1 on kx = 0, 2 elsewhere (FP64)."""
+    return 2.0 * t.sum(dtype=torch.float64).item() - t[..., 0].sum(dtype=torch.float64).item()
+
+
+def re_dot(a, b):
+    return a.real * b.real + a.imag * b.imag
+
+
+def test_mhd1024_invariants_and_dissipation(P, torch):
+    n, nu, eta, dt = N1024, 1e-3, 1e-3, 2.5e-4
+    kw = dict(spectrum=I.spectrum_c3, energy=0.5, kcut=KB, dtype=np.complex64)
+    st = torch.empty((6, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    st[:3] = embed(torch, I.random_solenoidal(64, 3, field=0, **kw), n, KB)
+    st[3:] = embed(torch, I.random_solenoidal(64, 3, field=1, **kw), n, KB)
+    plan = P.Plan(n, solver="mhd", precision="fp32", rk_order=2, nu=nu, eta=eta, dt=dt)
+    rhs = torch.empty_like(st)
+    plan.rhs(st, rhs)
+    torch.cuda.synchronize()
+    te = sum(wsum(torch, re_dot(st[c], rhs[c])) for c in range(6))
+    th = sum(wsum(torch, re_dot(st[c], rhs[c + 3]) + re_dot(st[c + 3], rhs[c])) for c in range(3))
+    se = sum(wsum(torch, st[c].abs() * rhs[c].abs()) for c in range(6))
+    sh = sum(wsum(torch, st[c].abs() * rhs[c + 3].abs() + st[c + 3].abs() * rhs[c].abs()) for c in range(3))
+    assert se > 0 and sh > 0
+    assert abs(te) < 1e-5 * se, (te, se)
+    assert abs(th) < 1e-5 * sh, (th, sh)
+    del rhs
+    # 5 steps of the benchmark configuration: dE = -int 2 (nu Z_u + eta Z_b) dt
+    plan.set_state(st[:3], field="u")
+    plan.set_state(st[3:], field="b")
+    ks = torch.fft.fftfreq(n, d=1.0 / n, device="cuda").to(torch.float32)
+    k2 = ks[:, None, None] ** 2 + ks[None, :, None] ** 2 + ks[None, None, : n // 2 + 1] ** 2
+
+    def dissipation():
+        plan.get_state("u", out=st[:3])
+        plan.get_state("b", out=st[3:])
+        zu = sum(wsum(torch, k2 * st[c].abs() ** 2) for c in range(3))
+        zb = sum(wsum(torch, k2 * st[c + 3].abs() ** 2) for c in range(3))
+        return nu * zu + eta * zb   # = -dE/dt with E = 1/2 sum w |.|^2
+
+    e = [sum(plan.energy())]
+    d = [dissipation()]
+    for _ in range(5):
+        plan.step(1)
+        e.append(sum(plan.energy()))
+        d.append(dissipation())
+    pred = -sum(dt * 0.5 * (d[i] + d[i + 1]) for i in range(5))
+    de = e[-1] - e[0]
+    assert pred < 0 and abs(de - pred) < 0.05 * abs(pred), (de, pred)
+    plan.close()
+    del st, k2
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------ ensemble, 96 runs
+def test_ensemble_96_runs(O, P, torch, tmp_path):
+    sizes = [48] * 32 + [64] * 48 + [96] * 16
+    nu, dt, ns = 1e-2, 1e-3, 3
+    init = [I.random_solenoidal(n, r, dtype=np.complex64) for r, n in enumerate(sizes)]
+    outs = {}
+    for mode in ("graph", "batched"):
+        ens = P.Ensemble(sizes, rk_order=4, nu=nu, dt=dt)
+        ens.autotune(str(tmp_path / "tune.json"))
+        for r, u in enumerate(init):
+            ens.set_state(r, u)
+        ens.set_mode(mode)
+        ens.step(ns)
+        outs[mode] = [ens.get_state(r) for r in range(len(sizes))]
+        ens.close()
+    for r in range(len(sizes)):
+        assert np.array_equal(outs["graph"][r], outs["batched"][r]), r
+    for r in (0, 32, 80):   # one run of each size
+        ref = O.step(init[r].astype(np.complex128), ns, dt=dt, nu=nu, rk=4)
+        assert rel(outs["graph"][r], ref) < 1e-5, (r, sizes[r])
+
+
+# ------------------------------------------------------------ FNO, batch 8
+def test_fno_full_config(P, torch):
+    import oracle.fno as F
+    cfg = dict(n=64, width=32, modes=12, layers=4, hidden=128)
+    theta = I.fno_init_params(seed=1, out_scale=0.5, **cfg).astype(np.float32).astype(np.float64)
+    x = np.random.default_rng(21).standard_normal((8, 3, 64, 64, 64)).astype(np.float32)
+    y_ref = F.forward(theta, x[7:].astype(np.float64), cfg)[0] - x[7]
+    xd = torch.from_numpy(x).cuda()
+    for mfma, tol in ((True, 2e-2), (False, 1e-5)):
+        fno = P.FNO(batch=8, mfma=mfma, **cfg)
+        fno.set_params(theta)
+        od = torch.empty_like(xd)
+        fno.forward(xd, od)
+        y = od[7].cpu().numpy().astype(np.float64) - x[7]
+        assert rel(y, y_ref) < tol, mfma
+        fno.close()
