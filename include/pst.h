@@ -160,6 +160,12 @@ pst_status pst_step(pst_plan *plan, int nsteps);
  * NONFINITE if either is NaN/Inf. */
 pst_status pst_energy(pst_plan *plan, double out[2]);
 
+/* Enstrophies Z = 1/2 <|curl v|^2> = 1/2 sum_k w |k|^2 |vhat|^2 of u and b
+ * (out[1] = 0 for NS), accumulated in double; with the energy they give the
+ * viscous energy loss rate dE/dt = -2 (nu Z_u + eta Z_b) of the unforced
+ * equations.  Synchronous.  NONFINITE if either is NaN/Inf. */
+pst_status pst_enstrophy(pst_plan *plan, double out[2]);
+
 /* Shell spectrum E(s) = 1/2 sum_{floor(|k|+1/2) = s} w |vhat|^2 for
  * s = 0..nshells-1 (double).  nshells must be >= floor(sqrt(3) K + 1/2) + 1.
  * Synchronous. */

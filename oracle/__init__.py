@@ -56,6 +56,8 @@ def lib():
         L.ora_step.restype = i
         L.ora_energy.argtypes = [i, P]
         L.ora_energy.restype = ctypes.c_double
+        L.ora_enstrophy.argtypes = [i, P]
+        L.ora_enstrophy.restype = ctypes.c_double
         L.ora_spectrum.argtypes = [i, P, P, i]
         _lib = L
     return _lib
@@ -169,6 +171,12 @@ def step(uhat, nsteps, *, dt, nu, rk=4, bhat=None, eta=None, fhat=None, kcut=Non
 def energy(vhat):
     vhat = _c128(vhat)
     return lib().ora_energy(vhat.shape[1], _ptr(vhat))
+
+
+def enstrophy(vhat):
+    """Z = 1/2 sum_k w |k|^2 |vhat|^2 (w = 1 on kx = 0 and kx = n/2, else 2)."""
+    vhat = _c128(vhat)
+    return lib().ora_enstrophy(vhat.shape[1], _ptr(vhat))
 
 
 def spectrum(vhat, nshells):

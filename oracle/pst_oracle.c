@@ -561,6 +561,30 @@ double ora_energy(int n, const double *vhat)
     return e;
 }
 
+/* Enstrophy Z = 1/2 sum_k w |k|^2 |vhat(k)|^2 (the mean of |curl v|^2 / 2 for
+ * a real field), pairwise-summed.                                            */
+double ora_enstrophy(int n, const double *vhat)
+{
+    long nh = NH(n);
+    int nxh = n / 2 + 1;
+    const cplx *v = (const cplx *)vhat;
+    double *t = (double *)malloc(sizeof(double) * (size_t)nh);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < nh; ++i) {
+        int x = (int)(i % nxh), y = (int)((i / nxh) % n), z = (int)(i / ((long)nxh * n));
+        long kx = x, ky = wn(y, n), kz = wn(z, n);
+        double s = 0;
+        for (int c = 0; c < 3; ++c) {
+            cplx q = v[c * nh + i];
+            s += creal(q) * creal(q) + cimag(q) * cimag(q);
+        }
+        t[i] = 0.5 * hweight(x, n) * (double)(kx * kx + ky * ky + kz * kz) * s;
+    }
+    double e = pairwise(t, nh);
+    free(t);
+    return e;
+}
+
 /* Shell index n = floor(|k| + 1/2). */
 static int shell_of(long k2) { return (int)floor(sqrt((double)k2) + 0.5); }
 

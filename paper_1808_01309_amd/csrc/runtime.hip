@@ -171,13 +171,17 @@ constexpr int RED_BLOCKS = 1024, RED_THREADS = 256;
 
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_energy_part(const cx<T>* __restrict__ st, Geo g, int c0,
-                                                             double* __restrict__ part) {
+                                                             double* __restrict__ part, int k2w) {
     __shared__ double sh[RED_THREADS];
     double acc = 0.0;
     const int64_t per = g.sc;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (int64_t)gridDim.x * blockDim.x) {
         const int kx = (int)(i / ((int64_t)g.M * g.M));
-        const double w = kx == 0 ? 1.0 : 2.0;
+        double w = kx == 0 ? 1.0 : 2.0;
+        if (k2w) {  // enstrophy: weight |k|^2
+            const int ky = k_of_j((int)((i / g.M) % g.M), g), kz = k_of_j((int)(i % g.M), g);
+            w *= (double)(kx * kx + ky * ky + kz * kz);
+        }
         double s = 0.0;
         for (int c = 0; c < 3; ++c) {
             const cx<T> v = st[(int64_t)(c0 + c) * per + i];
@@ -650,30 +654,35 @@ extern "C" pst_status pst_step(pst_plan* P, int nsteps) {
 
 // --------------------------------------------------------------- diagnostics
 template <typename T>
-static void launch_energy(pst_plan* P, int c0, double* out) {
+static void launch_energy(pst_plan* P, int c0, double* out, int k2w) {
     KTimer tm(P, PST_K_OTHER);
     hipLaunchKernelGGL((k_energy_part<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, P->stream, (const cx<T>*)P->U,
-                       P->geo, c0, P->red);
+                       P->geo, c0, P->red, k2w);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(RED_THREADS), 0, P->stream, P->red, RED_BLOCKS, out, 0.5);
 }
 
-extern "C" pst_status pst_energy(pst_plan* P, double out[2]) {
+// energy (k2w = 0) or enstrophy (k2w = 1) of u and b
+static pst_status quadratic_diag(pst_plan* P, double out[2], int k2w, const char* what) {
     if (!P || !out) return P ? fail(P, PST_ERR_INVALID_ARG, "out is NULL") : PST_ERR_INVALID_ARG;
     double* res = P->red + RED_BLOCKS + MAX_SHELLS;
     for (int grp = 0; grp < P->ncomp / 3; ++grp) {
-        if (P->p.precision == PST_FP64) launch_energy<double>(P, grp * 3, res + grp);
-        else launch_energy<float>(P, grp * 3, res + grp);
+        if (P->p.precision == PST_FP64) launch_energy<double>(P, grp * 3, res + grp, k2w);
+        else launch_energy<float>(P, grp * 3, res + grp, k2w);
     }
-    pst_status s = check_launch(P, "energy");
+    pst_status s = check_launch(P, what);
     if (s) return s;
     double h[2] = {0.0, 0.0};
     HIPCHK(P, hipMemcpyAsync(h, res, sizeof(double) * (P->ncomp / 3), hipMemcpyDeviceToHost, P->stream));
     HIPCHK(P, hipStreamSynchronize(P->stream));
     out[0] = h[0];
     out[1] = P->ncomp == 6 ? h[1] : 0.0;
-    if (!isfinite(out[0]) || !isfinite(out[1])) return fail(P, PST_ERR_NONFINITE, "energy is not finite");
+    if (!isfinite(out[0]) || !isfinite(out[1])) return fail(P, PST_ERR_NONFINITE, "%s is not finite", what);
     return PST_OK;
 }
+
+extern "C" pst_status pst_energy(pst_plan* P, double out[2]) { return quadratic_diag(P, out, 0, "energy"); }
+
+extern "C" pst_status pst_enstrophy(pst_plan* P, double out[2]) { return quadratic_diag(P, out, 1, "enstrophy"); }
 
 extern "C" pst_status pst_spectrum(pst_plan* P, int field, double* Ek, int nshells) {
     if (!P) return PST_ERR_INVALID_ARG;

@@ -65,7 +65,7 @@ lib.pst_plan_destroy.argtypes = [_P]
 lib.pst_plan_destroy.restype = None
 for _name, _args in [("pst_set_state", [_P, _I, _I, _P, _I]), ("pst_get_state", [_P, _I, _I, _P, _I]),
                      ("pst_set_forcing", [_P, _P, _I]), ("pst_rhs", [_P, _P, _P]), ("pst_step", [_P, _I]),
-                     ("pst_energy", [_P, _P]), ("pst_spectrum", [_P, _I, _P, _I]),
+                     ("pst_energy", [_P, _P]), ("pst_enstrophy", [_P, _P]), ("pst_spectrum", [_P, _I, _P, _I]),
                      ("pst_fft_r2c", [_P, _P, _P, _I]), ("pst_fft_c2r", [_P, _P, _P, _I]),
                      ("pst_query", [_P, ctypes.POINTER(pst_info)]),
                      ("pst_timer_read", [_P, _P, _P, _I])]:
@@ -114,7 +114,7 @@ EXPORTED = ["pst_fno_create", "pst_fno_destroy", "pst_fno_last_error", "pst_fno_
             "pst_ensemble_autotune", "pst_ensemble_set_schedule", "pst_ensemble_query", "pst_ensemble_project",
             "pst_ensemble_diagnostics", "pst_ensemble_rel_l2",
             "pst_status_str", "pst_last_error", "pst_supported_n", "pst_plan_create", "pst_plan_destroy",
-            "pst_set_state", "pst_get_state", "pst_set_forcing", "pst_rhs", "pst_step", "pst_energy",
+            "pst_set_state", "pst_get_state", "pst_set_forcing", "pst_rhs", "pst_step", "pst_energy", "pst_enstrophy",
             "pst_spectrum", "pst_fft_r2c", "pst_fft_c2r", "pst_query", "pst_timer_read"]
 
 
@@ -239,6 +239,11 @@ class Plan:
     def energy(self):
         out = np.zeros(2, np.float64)
         self._check(lib.pst_energy(self._h, out.ctypes.data_as(_P)))
+        return float(out[0]), float(out[1])
+
+    def enstrophy(self):
+        out = np.zeros(2, np.float64)
+        self._check(lib.pst_enstrophy(self._h, out.ctypes.data_as(_P)))
         return float(out[0]), float(out[1])
 
     def spectrum(self, field="u", nshells=None):

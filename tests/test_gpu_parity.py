@@ -230,6 +230,20 @@ def test_energy_spectrum(O, P, torch, prec):
     s = plan.spectrum()
     ref = O.spectrum(uq, len(s))
     assert np.abs(s - ref).max() < 1e-13 * e
+    z = plan.enstrophy()
+    assert z[1] == 0.0 and abs(z[0] - O.enstrophy(uq)) < 1e-13 * z[0]
+
+
+def test_mhd_enstrophy(O, P, torch):
+    n = 32
+    plan = P.Plan(n, solver="mhd", precision="fp64")
+    u = I.random_solenoidal(n, 31, spectrum=I.spectrum_c3, energy=0.5)
+    b = I.random_solenoidal(n, 31, field=1, spectrum=I.spectrum_c3, energy=0.5)
+    plan.set_state(u, "u")
+    plan.set_state(b, "b")
+    zu, zb = plan.enstrophy()
+    assert abs(zu - O.enstrophy(plan.get_state("u"))) < 1e-13 * zu
+    assert abs(zb - O.enstrophy(plan.get_state("b"))) < 1e-13 * zb
 
 
 def test_bitwise_repeatable(P, torch):
@@ -270,4 +284,7 @@ def test_errors_on_gpu(P, torch):
     plan.set_state(np.full((3, 32, 32, 17), np.nan, np.complex64))
     with pytest.raises(P.PstError) as ei:
         plan.energy()
+    assert ei.value.status == P.PST_ERR_NONFINITE
+    with pytest.raises(P.PstError) as ei:
+        plan.enstrophy()
     assert ei.value.status == P.PST_ERR_NONFINITE

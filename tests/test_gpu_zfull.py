@@ -132,6 +132,8 @@ def test_mhd1024_invariants_and_dissipation(P, torch):
         plan.get_state("b", out=st[3:])
         zu = sum(wsum(torch, k2 * st[c].abs() ** 2) for c in range(3))
         zb = sum(wsum(torch, k2 * st[c + 3].abs() ** 2) for c in range(3))
+        pz = plan.enstrophy()   # 1/2 sum w |k|^2 |.|^2, from the library
+        assert abs(pz[0] - 0.5 * zu) < 1e-5 * pz[0] and abs(pz[1] - 0.5 * zb) < 1e-5 * pz[1]
         return nu * zu + eta * zb   # = -dE/dt with E = 1/2 sum w |.|^2
 
     e = [sum(plan.energy())]

@@ -267,6 +267,28 @@ def test_energy_parseval_and_spectrum(O):
     assert sv[2] == pytest.approx(0.25, abs=1e-16) and abs(sv.sum() - 0.25) < 1e-16
 
 
+def test_enstrophy_closed_forms(O):
+    """Z = 1/2 sum w |k|^2 |vhat|^2: Taylor-Green (every mode at |k|^2 = 3,
+    E = 1/8) gives 3/8; one mode at (2, 1, 0) of amplitude 1/2 gives
+    1/2 * 2 * 5 * 1/4; a random field matches 1/2 <|curl u|^2> with the curl
+    taken by numpy's FFT in physical space."""
+    n = 16
+    assert abs(O.enstrophy(I.taylor_green_spec(n)) - 3.0 / 8.0) < 1e-15
+    v = np.zeros((3, n, n, n // 2 + 1), np.complex128)
+    v[0, 0, 1, 2] = 0.5
+    assert O.enstrophy(v) == pytest.approx(1.25, abs=1e-15)
+    u = I.random_solenoidal(n, 6)
+    ur = O.c2r_vec(u)
+    k = np.fft.fftfreq(n, 1.0 / n)
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+
+    def d(f, kk):
+        return np.real(np.fft.ifftn(1j * kk * np.fft.fftn(f)))
+
+    w = np.stack([d(ur[2], ky) - d(ur[1], kz), d(ur[0], kz) - d(ur[2], kx), d(ur[1], kx) - d(ur[0], ky)])
+    assert abs(O.enstrophy(u) - 0.5 * np.mean(np.sum(w ** 2, axis=0))) < 1e-13 * O.enstrophy(u)
+
+
 def test_random_field_is_solenoidal_and_real(O):
     n = 24
     u = I.random_solenoidal(n, 8)
