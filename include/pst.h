@@ -58,7 +58,12 @@ typedef enum {
 
 typedef enum { PST_NS = 0, PST_MHD = 1 } pst_solver;
 typedef enum { PST_FP32 = 0, PST_FP64 = 1 } pst_precision;
-typedef enum { PST_DEALIAS_CUBE = 0 } pst_dealias;
+/* Dealiasing of the nonlinear terms (2/3 rule, K = ceil(n/3) - 1):
+ * CUBE keeps max(|kx|, |ky|, |kz|) <= K; SPHERE keeps |k|^2 <= K^2.  The state
+ * always holds the cube; under SPHERE the modes between sphere and cube get
+ * no nonlinear term (they evolve by the linear part alone).  Ensembles use the
+ * cube. */
+typedef enum { PST_DEALIAS_CUBE = 0, PST_DEALIAS_SPHERE = 1 } pst_dealias;
 typedef enum { PST_FIELD_U = 0, PST_FIELD_B = 1 } pst_field;
 typedef enum { PST_SPACE_PHYS = 0, PST_SPACE_SPEC = 1 } pst_space;
 typedef enum { PST_MEM_HOST = 0, PST_MEM_DEVICE = 1 } pst_mem;

@@ -383,6 +383,8 @@ extern "C" pst_status pst_ensemble_create(int nruns, const int* n, const pst_par
     if (!(common->dt > 0.0) || !(common->nu >= 0.0) || !isfinite(common->dt) || !isfinite(common->nu))
         return efail(nullptr, PST_ERR_INVALID_ARG, "dt must be > 0 and nu >= 0");
     if (common->flags != 0) return efail(nullptr, PST_ERR_UNSUPPORTED, "flags are not supported for ensembles");
+    if (common->dealias != PST_DEALIAS_CUBE)
+        return efail(nullptr, PST_ERR_UNSUPPORTED, "ensembles use the cube truncation");
     // classes in descending n: the persistent kernel hands out the most
     // expensive work units first
     std::map<int, int, std::greater<int>> cls_of;

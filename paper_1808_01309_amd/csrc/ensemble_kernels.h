@@ -123,6 +123,7 @@ __device__ __forceinline__ void ens_unit_v(const EnsClass<T>& c, int pass, int s
             ra.F = nullptr;
             ra.kf = -1;
             ra.lin_only = 0;
+            ra.sph2 = -1;
             zfwd_body<T, LC, ENS_NT, false>(A, c.tw, g, ra, mode, lu, tid, sm);
         } break;
     }

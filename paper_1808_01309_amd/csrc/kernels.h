@@ -85,6 +85,7 @@ struct RkArgs {
     const cx<T>* F;    // forcing box or null
     int kf;
     int lin_only;
+    int sph2;          // spherical truncation: nonlinear terms kept for |k|^2 <= sph2; -1: the cube
 };
 
 // ------------------------------------------------------------ zinv + curl
@@ -393,9 +394,11 @@ __device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<
         const int k2 = kx * kx + iky * iky + ikz * ikz;
         const int64_t idx = lin * geo.M + j;
         cx<T> n0 = cscale(v[0][e], scale), n1 = cscale(v[1][e], scale), n2 = cscale(v[2][e], scale);
-        // projection onto divergence-free fields: n - k (k . n) / |k|^2, zero at k = 0
+        // projection onto divergence-free fields: n - k (k . n) / |k|^2, zero at
+        // k = 0 and, with spherical truncation, outside the sphere
+        const bool cut = ra.sph2 >= 0 && k2 > ra.sph2;
         cx<T> o[3];
-        if (k2 == 0) {
+        if (k2 == 0 || cut) {
             o[0] = o[1] = o[2] = czero<T>();
         } else {
             const T ik2 = T(1) / T(k2);
@@ -421,7 +424,7 @@ __device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<
             b[0] = mul_i(cx<T>{fky * m2.x - fkz * m1.x, fky * m2.y - fkz * m1.y});
             b[1] = mul_i(cx<T>{fkz * m0.x - fkx * m2.x, fkz * m0.y - fkx * m2.y});
             b[2] = mul_i(cx<T>{fkx * m1.x - fky * m0.x, fkx * m1.y - fky * m0.y});
-            if (ra.lin_only) b[0] = b[1] = b[2] = czero<T>();
+            if (ra.lin_only || cut) b[0] = b[1] = b[2] = czero<T>();
 #pragma unroll
             for (int c = 0; c < 3; ++c) rk_apply(mode, ra, 1, (3 + c) * geo.sc + idx, k2, b[c]);
         }
@@ -721,6 +724,7 @@ struct Impl {
         ra.F = (const cx<T>*)P->force;
         ra.kf = P->kf;
         ra.lin_only = (P->p.flags & PST_FLAG_LINEAR_ONLY) ? 1 : 0;
+        ra.sph2 = P->p.dealias == PST_DEALIAS_SPHERE ? g.K * g.K : -1;
         const unsigned nb = (unsigned)line_units<LC, LINE_BLOCK>(g);
         if (P->ncomp == 6)
             hipLaunchKernelGGL((k_zfwd<T, LC, true>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,

@@ -337,7 +337,8 @@ extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst
     if (!(p->nu >= 0.0) || !isfinite(p->nu)) return fail(nullptr, PST_ERR_INVALID_ARG, "nu must be >= 0");
     if (p->solver == PST_MHD && (!(p->eta >= 0.0) || !isfinite(p->eta)))
         return fail(nullptr, PST_ERR_INVALID_ARG, "eta must be >= 0");
-    if (p->dealias != PST_DEALIAS_CUBE) return fail(nullptr, PST_ERR_UNSUPPORTED, "dealias %d", p->dealias);
+    if (p->dealias != PST_DEALIAS_CUBE && p->dealias != PST_DEALIAS_SPHERE)
+        return fail(nullptr, PST_ERR_UNSUPPORTED, "dealias %d", p->dealias);
     if (p->flags & ~(unsigned)(PST_FLAG_LINEAR_ONLY | PST_FLAG_TIMERS))
         return fail(nullptr, PST_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
     if (!pst_supported_n(p->n)) return fail(nullptr, PST_ERR_UNSUPPORTED_N, "n = %d not supported", p->n);

@@ -152,10 +152,11 @@ class Plan:
     """One solver plan (pst_plan_create ... pst_plan_destroy)."""
 
     def __init__(self, n, solver="ns", precision="fp32", rk_order=4, nu=0.0, eta=None, dt=1e-3,
-                 linear_only=False, timers=False, stream=None):
+                 linear_only=False, timers=False, stream=None, dealias="cube"):
         p = pst_params(n=n, solver=PST_MHD if solver == "mhd" else PST_NS,
                        precision=PST_FP64 if precision == "fp64" else PST_FP32, rk_order=rk_order,
-                       nu=nu, eta=nu if eta is None else eta, dt=dt, dealias=0,
+                       nu=nu, eta=nu if eta is None else eta, dt=dt,
+                       dealias={"cube": 0, "sphere": 1}[dealias],
                        flags=(PST_FLAG_LINEAR_ONLY if linear_only else 0) | (PST_FLAG_TIMERS if timers else 0))
         self.params = p
         self.n = n

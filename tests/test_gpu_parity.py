@@ -128,6 +128,43 @@ def test_mhd_rhs(O, P, torch, n, prec):
     assert max(rel_per_field(got[3:], rb)) < TOL[prec]
 
 
+def sphere_only(u):
+    """Zero the modes outside the sphere |k| <= K (the same input for both sides)."""
+    n = u.shape[1]
+    kx, ky, kz = I.wavenumbers(n)
+    K = I.kcut_23(n)
+    return u * ((kx ** 2 + ky ** 2 + kz ** 2) <= K * K)[None]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [24, 48])
+def test_sphere_truncation(O, P, torch, n, prec):
+    """Spherical 2/3 truncation: NS and MHD right-hand sides and forced RK4 steps."""
+    u = sphere_only(I.random_solenoidal(n, 50 + n))
+    f = I.forcing_shells(n, 50 + n)
+    plan = P.Plan(n, precision=prec, dealias="sphere")
+    plan.set_forcing(f)
+    got = _rhs(P, torch, plan, u)
+    ref = O.ns_rhs(u, f, sphere=True)
+    assert max(rel_per_field(got, ref)) < TOL[prec]
+    # the sphere removes modes the cube keeps
+    assert rel(ref, O.ns_rhs(u, f)) > 1e-3
+    nu, dt = 2e-3 * 512 / n, 5e-3
+    plan = P.Plan(n, precision=prec, rk_order=4, nu=nu, dt=dt, dealias="sphere")
+    plan.set_state(u)
+    plan.set_forcing(f)
+    plan.step(3)
+    ref = O.step(u, 3, dt=dt, nu=nu, rk=4, fhat=f, sphere=True)
+    assert max(rel_per_field(plan.get_state(), ref)) < TOL[prec]
+    b = sphere_only(I.random_solenoidal(n, 60 + n, field=1, spectrum=I.spectrum_c3, energy=0.5))
+    um = sphere_only(I.random_solenoidal(n, 60 + n, spectrum=I.spectrum_c3, energy=0.5))
+    plan = P.Plan(n, solver="mhd", precision=prec, dealias="sphere")
+    got = _rhs(P, torch, plan, np.concatenate([um, b]))
+    ru, rb = O.mhd_rhs(um, b, sphere=True)
+    assert max(rel_per_field(got[:3], ru)) < TOL[prec]
+    assert max(rel_per_field(got[3:], rb)) < TOL[prec]
+
+
 def test_taylor_green_closed_form_on_gpu(P, torch):
     n = 32
     plan = P.Plan(n, precision="fp64")
