@@ -8,10 +8,17 @@ RK4 with the viscous integrating factor; dt = 5e-4.  The state is resident in
 HBM before the timed region; each timed step is one full pass of the hot path
 (4 right-hand sides of 5 kernels each, with the RK update fused).
 
-Prints one JSON line.  Also reported: the standalone 3D r2c / c2r transforms
-of 3 fields at 512^3 per pass in GB/s, the roofline of the dominant kernel
-(algorithmic bytes per launch / HIP-event-timed launch duration), and the FP64
-CPU oracle timed on a bounded sample on this host.
+Defaults: 2 warm-up + 18 timed steps (the workload's 20 steps); `value` is
+the mean over the timed steps, the per-step median is reported too.
+
+Prints one JSON line.  Also reported (under "extra"): a plain device copy's
+bandwidth; the standalone 3D r2c / c2r transforms of 3 fields at 512^3 per pass
+in GB/s; the MHD 1024^3 RK2 step; the 96-run ensemble in every execution mode;
+the FNO's forward pass and training step at 64^3; the surrogate's speed-up
+(from its committed run unless --surrogate); the roofline of the dominant
+kernel (algorithmic bytes per launch / HIP-event-timed launch duration, as a
+fraction of 8 TB/s and of the copy bandwidth) and the FP64 CPU oracle timed on
+one step on this host.
 """
 from __future__ import annotations
 
@@ -35,7 +42,7 @@ KINDS = ["zinv", "yinv", "xpass", "yfwd", "zfwd"]
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=18)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-fp64", action="store_true")
@@ -43,6 +50,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-fno", action="store_true")
+    ap.add_argument("--no-mhd", action="store_true")
     ap.add_argument("--surrogate", action="store_true",
                     help="run the whole surrogate pipeline (data, ~70 s of training, evaluation, timed "
                          "hybrid rollout) instead of reporting its committed summary")
@@ -51,19 +59,20 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_bytes(n, esz, rk):
-    """Algorithmic HBM bytes per launch of each solver kernel (Navier-Stokes):
-    every array element a pass must read or write, once."""
+def kernel_bytes(n, esz, rk, mhd=False):
+    """Algorithmic HBM bytes per launch of each solver kernel: every array
+    element a pass must read or write, once (MHD: twice the fields)."""
     K = -(-n // 3) - 1
     M, nxk = 2 * K + 1, K + 1
     sc, sa, sb = nxk * M * M, nxk * M * n, nxk * n * n
     rk_arrays = 13.0 / 4.0 if rk == 4 else 5.0 / 2.0  # state-sized arrays touched per stage update
+    g = 2 if mhd else 1
     return {
-        "zinv": (3 * sc + 6 * sa) * esz,
-        "yinv": (6 * sa + 6 * sb) * esz,
-        "xpass": (6 * sb + 3 * sb) * esz,
-        "yfwd": (3 * sb + 3 * sa) * esz,
-        "zfwd": (3 * sa + rk_arrays * 3 * sc) * esz,
+        "zinv": g * (3 * sc + 6 * sa) * esz,
+        "yinv": g * (6 * sa + 6 * sb) * esz,
+        "xpass": g * (6 * sb + 3 * sb) * esz,
+        "yfwd": g * (3 * sb + 3 * sa) * esz,
+        "zfwd": g * (3 * sa + rk_arrays * 3 * sc) * esz,
     }
 
 
@@ -75,6 +84,23 @@ def fft_bytes(n, nf, esz_c):
     return {"fftx": real + cplx, "ffty": 2 * cplx, "fftz": 2 * cplx}
 
 
+def timed_steps(plan, torch, steps):
+    """Runs `steps` steps between two device synchronisations; returns the wall
+    ms per step and the per-step durations from events on the plan's stream
+    (torch's current stream)."""
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record()
+    for i in range(steps):
+        plan.step(1)
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    return (t1 - t0) * 1e3 / steps, per
+
+
 def run_solver(pst, torch, I, n, prec, steps, warmup):
     plan = pst.Plan(n, precision=prec, rk_order=4, nu=2e-3, dt=5e-4, timers=True)
     cdt = np.complex128 if prec == "fp64" else np.complex64
@@ -83,16 +109,72 @@ def run_solver(pst, torch, I, n, prec, steps, warmup):
     plan.step(warmup)
     torch.cuda.synchronize()
     plan.timers(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.step(steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms, per = timed_steps(plan, torch, steps)
     tm = plan.timers(reset=True)
     e = plan.energy()[0]
     info = plan.query()
+    info["median_step_ms"] = float(np.median(per))
     plan.close()
-    return (t1 - t0) * 1e3 / steps, tm, e, info
+    return ms, tm, e, info
+
+
+def band_limited_field(torch, I, n, seed, field, spectrum, energy, kb=24):
+    """Random-phase solenoidal field whose spectrum is negligible beyond |k_i| = kb
+    (E ~ k^2 exp(-(k/3)^2) is below 1e-25 there): generated on a 64^3 grid with
+    the cube cut at kb and placed into the n^3 layout on the device (the
+    counter-based generator gives every mode the same value on any grid)."""
+    m = 64
+    small = torch.from_numpy(I.random_solenoidal(m, seed, field=field, spectrum=spectrum, energy=energy,
+                                                 kcut=kb, dtype=np.complex64)).cuda()
+    big = torch.zeros((3, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    for bz, sz in ((slice(0, kb + 1), slice(0, kb + 1)), (slice(n - kb, n), slice(m - kb, m))):
+        for by, sy in ((slice(0, kb + 1), slice(0, kb + 1)), (slice(n - kb, n), slice(m - kb, m))):
+            big[:, bz, by, :kb + 1] = small[:, sz, sy, :kb + 1]
+    return big
+
+
+def run_mhd(pst, torch, I, n=1024, steps=5, warmup=1):
+    """MHD 1024^3 FP32, random-phase u and b with E(k) ~ k^2 exp(-(k/3)^2),
+    E_u = E_b = 1/2, nu = eta = 1e-3, RK2, dt = 2.5e-4: ms per step and per pass."""
+    plan = pst.Plan(n, solver="mhd", precision="fp32", rk_order=2, nu=1e-3, eta=1e-3, dt=2.5e-4, timers=True)
+    for f, name in ((0, "u"), (1, "b")):
+        st = band_limited_field(torch, I, n, 3, f, I.spectrum_c3, 0.5)
+        plan.set_state(st, field=name)
+        del st
+    torch.cuda.empty_cache()
+    plan.step(warmup)
+    torch.cuda.synchronize()
+    plan.timers(reset=True)
+    ms, per = timed_steps(plan, torch, steps)
+    tm = plan.timers(reset=True)
+    kb = kernel_bytes(n, 8, 2, mhd=True)
+    kern = {k: {"ms": tm[k][0] / max(tm[k][1], 1), "launches": tm[k][1]} for k in KINDS}
+    for k in KINDS:
+        kern[k]["GB_s"] = kb[k] / kern[k]["ms"] / 1e6
+    res = {"n": n, "precision": "fp32", "rk_order": 2, "steps": steps, "ms_per_step": ms,
+           "median_step_ms": float(np.median(per)), "kernels": kern,
+           "effective_GB_s": 2 * sum(kb.values()) / ms / 1e6, "energy_end": plan.energy()}
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def copy_bandwidth(torch, gib=4, reps=5):
+    """A plain device-to-device copy of `gib` GiB: read + write bytes per second."""
+    src = torch.empty(gib << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (gib << 30) / ms / 1e6
 
 
 def run_fft(pst, torch, n, prec, reps=5, nf=3):
@@ -176,20 +258,31 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n):
-    """The FP64 oracle (untuned) on this host: one Navier-Stokes right-hand side
-    at n^3 (one of the four stages of an RK4 step), scaled x4 to ms per step."""
+    """The FP64 oracle (untuned) on this host: one whole RK4 step (four
+    right-hand sides of 9 textbook 3D FFTs each, products, projection, Lawson
+    updates) of the same 512^3 workload."""
     import oracle as O
     from paper_1808_01309_amd import inputs as I
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     u = I.random_solenoidal(n, 1)
     f = I.forcing_shells(n, 1)
     t0 = time.perf_counter()
-    O.ns_rhs(u, f)
+    O.step(u, 1, dt=5e-4, nu=2e-3, rk=4, fhat=f)
     dt = time.perf_counter() - t0
-    return {"value": dt * 4e3, "unit": "ms/RK4 step", "cores": threads, "kind": "oracle",
-            "sample": f"one FP64 right-hand side (9 textbook 3D FFTs + products + projection) at "
-                      f"{n}^3 took {dt:.2f} s; x4 stages per RK4 step (stage updates excluded)"}
+    return {"value": dt * 1e3, "unit": "ms/RK4 step", "cores": threads, "kind": "oracle",
+            "sample": f"one FP64 RK4 step of the {n}^3 forced Navier-Stokes workload (4 right-hand sides) "
+                      f"took {dt:.2f} s on {threads} threads of {cpu_model()}"}
 
 
 FNO_CFG = dict(n=64, width=32, modes=12, layers=4, hidden=128)
@@ -252,6 +345,8 @@ def main():
     from paper_1808_01309_amd import pst
 
     n = a.n
+    print("[bench] device copy bandwidth (4 GiB)", file=sys.stderr, flush=True)
+    copy_gbs = copy_bandwidth(torch)
     if a.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -260,7 +355,8 @@ def main():
         del src, dst
     print(f"[bench] n={n} fp32 solver: warmup {a.warmup}, timed {a.steps}", file=sys.stderr, flush=True)
     ms32, tm32, e32, info = run_solver(pst, torch, I, n, "fp32", a.steps, a.warmup)
-    out_extra = {"fp32": {"ms_per_step": ms32, "energy_end": e32}}
+    out_extra = {"copy_GB_s": copy_gbs,
+                 "fp32": {"ms_per_step": ms32, "median_step_ms": info["median_step_ms"], "energy_end": e32}}
     per32 = {k: tm32[k][0] / max(tm32[k][1], 1) for k in KINDS}
     kb32 = kernel_bytes(n, 8, 4)
     out_extra["fp32"]["kernels"] = {k: {"ms": per32[k], "GB_s": kb32[k] / per32[k] / 1e6,
@@ -270,10 +366,10 @@ def main():
     out_extra["fp32"]["algorithmic_GB_per_step"] = step_bytes32 / 1e9
     if not a.no_fp64:
         print(f"[bench] n={n} fp64 solver", file=sys.stderr, flush=True)
-        ms64, tm64, e64, _ = run_solver(pst, torch, I, n, "fp64", a.steps, a.warmup)
+        ms64, tm64, e64, info64 = run_solver(pst, torch, I, n, "fp64", a.steps, a.warmup)
         per64 = {k: tm64[k][0] / max(tm64[k][1], 1) for k in KINDS}
         kb64 = kernel_bytes(n, 16, 4)
-        out_extra["fp64"] = {"ms_per_step": ms64, "energy_end": e64,
+        out_extra["fp64"] = {"ms_per_step": ms64, "median_step_ms": info64["median_step_ms"], "energy_end": e64,
                              "kernels": {k: {"ms": per64[k], "GB_s": kb64[k] / per64[k] / 1e6,
                                              "launches": tm64[k][1]} for k in KINDS},
                              "effective_GB_s": 4 * sum(kb64.values()) / ms64 / 1e6}
@@ -290,6 +386,9 @@ def main():
     if not a.no_ensemble:
         print("[bench] ensemble: 96 runs (48^3, 64^3, 96^3), 200 RK4 steps", file=sys.stderr, flush=True)
         out_extra["ensemble"] = run_ensemble(pst, torch, I)
+    if not a.no_mhd:
+        print("[bench] MHD 1024^3 FP32 RK2 (5 steps)", file=sys.stderr, flush=True)
+        out_extra["mhd1024"] = run_mhd(pst, torch, I)
     if not a.no_fno:
         print("[bench] FNO surrogate forward / training step (64^3, batch 8)", file=sys.stderr, flush=True)
         out_extra["fno"] = run_fno(pst, torch, I)
@@ -298,7 +397,8 @@ def main():
     dom = max(KINDS, key=lambda k: tm32[k][0])
     ach = kb32[dom] / per32[dom] / 1e6
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": traffic_from_profiles(dom, n, "fp32"),
+            "frac": round(ach / PEAK_HBM_GBS, 4), "frac_of_copy": round(ach / copy_gbs, 4),
+            "traffic": traffic_from_profiles(dom, n, "fp32"),
             "algorithmic_bytes_per_launch": kb32[dom], "avg_launch_ms": per32[dom]}
     cpu = None
     if not a.no_cpu:

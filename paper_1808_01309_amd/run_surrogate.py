@@ -87,6 +87,7 @@ def run(argv=None):
     res["summary"] = {
         "speedup": h.get("speedup"),
         "fno_forward_ms_batch": res["fno_forward_ms_batch"],
+        "plain_solver_ms_per_10_steps": h["t_plain_s"] * 1e3 / h["apps"] if "t_plain_s" in h else None,
         "max_audited_window_err": max(h["audit_err"]) if h["audit_err"] else None,
         "accepted_windows": h["apps"] - h["solver_windows"] - h["audit_fail"] - h["guard_fail"],
         "solver_windows": h["solver_windows"], "audit_fail": h["audit_fail"], "guard_fail": h["guard_fail"],
