@@ -40,11 +40,8 @@ static const EnsKernels* ens_kernels(int v) {
 }
 
 __global__ void k_ens_reset(unsigned* bar, int* err) {
-    if (threadIdx.x == 0) {
-        bar[0] = 0u;
-        bar[1] = 0u;
-        err[0] = 0;
-    }
+    for (int i = threadIdx.x; i < ENS_BAR_WORDS; i += blockDim.x) bar[i] = 0u;
+    if (threadIdx.x == 0) err[0] = 0;
 }
 
 template <typename T>
@@ -445,7 +442,7 @@ extern "C" pst_status pst_ensemble_create(int nruns, const int* n, const pst_par
         maxspec = std::max(maxspec, (size_t)3 * h.n * h.n * (h.n / 2 + 1) * es);
         if (!ok) break;
     }
-    ok = ok && alloc((void**)&E->desc_dev, sizeof(EnsDesc<float>)) && alloc((void**)&E->bar, 64) && alloc((void**)&E->err, 64) && alloc((void**)&E->eout, sizeof(double) * 2 * nruns) &&
+    ok = ok && alloc((void**)&E->desc_dev, sizeof(EnsDesc<float>)) && alloc((void**)&E->bar, sizeof(unsigned) * ENS_BAR_WORDS) && alloc((void**)&E->err, 64) && alloc((void**)&E->eout, sizeof(double) * 2 * nruns) &&
          alloc(&E->scratch, maxspec);
     E->scratch_bytes = maxspec;
     if (!ok) {

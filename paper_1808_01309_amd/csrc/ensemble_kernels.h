@@ -142,41 +142,54 @@ __device__ __forceinline__ void ens_unit(const EnsClass<T>& c, int pass, int sv,
 
 // Device-wide barrier with a bounded wait.  Returns false (on every thread of
 // the block) if the barrier failed or another block reported a failure.
-// One agent-scope release fence per block before it arrives and one acquire
-// fence after it leaves (each writes back / invalidates the non-coherent
-// caches, so they are kept out of the polling loop, which reads the
-// generation counter with relaxed atomics).  The last block to arrive
-// acquires everyone's writes, resets the counter and releases the new
-// generation.
+// Arrivals are counted in ENS_BAR_SUB sub-counters (block b in group
+// b % ENS_BAR_SUB), each on its own cache line, so that no single atomic
+// location serialises every block; the last arrival of a group then counts the
+// group in, and the last group releases a new generation, which the waiting
+// blocks poll with relaxed loads.  One agent-scope release fence per block
+// before it arrives and one acquire fence after it leaves (each writes back /
+// invalidates non-coherent caches, so none sits in the polling loop); group
+// and final leaders acquire what they count in and release it onwards.
+//   bar[0]: groups arrived; bar[32]: generation; bar[64 + 32 g]: group g
+constexpr int ENS_BAR_SUB = 16;
+constexpr int ENS_BAR_WORDS = 32 * (2 + ENS_BAR_SUB);
 __device__ __forceinline__ bool grid_barrier(unsigned* bar, int* err, unsigned nblocks, long long limit) {
     __shared__ int ok_sh;
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned gen = __hip_atomic_load(&bar[32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned g = blockIdx.x % ENS_BAR_SUB;
+        const unsigned ngroups = nblocks < (unsigned)ENS_BAR_SUB ? nblocks : (unsigned)ENS_BAR_SUB;
+        const unsigned gsize = (nblocks - g + ENS_BAR_SUB - 1) / ENS_BAR_SUB;
+        unsigned* sub = &bar[64 + 32 * g];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            long long spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 0;
-                    break;
-                }
-                if (++spins > limit) {
-                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
+        const unsigned a = __hip_atomic_fetch_add(sub, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == gsize - 1) {
+            __hip_atomic_store(sub, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            const unsigned t = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == ngroups - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_fetch_add(&bar[32], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
+        long long spins = 0;
+        while (__hip_atomic_load(&bar[32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            if (++spins > limit) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         ok_sh = ok;
     }
     __syncthreads();
