@@ -59,6 +59,14 @@ template <typename T, class CF, int NT> constexpr int line_lds() { return (NT / 
 template <typename T, class CF, int NT> constexpr int tile_lds() { return (NT / (CF::G * CF::TL)) * CF::N * (CF::TL + 1); }
 template <int N, int TL> constexpr int ztiles() { return (N + TL - 1) / TL; }
 
+// Workgroups are dispatched to the 8 XCDs round-robin; xcd_unit renumbers
+// them so that each XCD works through one contiguous range of units (a
+// bijection on [0, gridDim.x)).
+__device__ __forceinline__ int64_t xcd_unit() {
+    const int64_t nb = gridDim.x, b = blockIdx.x, x = b % 8, q = nb / 8, r = nb % 8;
+    return x * q + (x < r ? x : r) + b / 8;
+}
+
 // Work units: a line body handles NT / G lines per unit, a tile body
 // NT / (G TL) tiles per unit.
 template <class CF, int NT> inline int64_t line_units(const Geo& g) {
@@ -203,7 +211,9 @@ __global__ __launch_bounds__((CF::G * CF::TL)) void k_ypass(const cx<T>* __restr
                                                           const cx<T>* __restrict__ tw, Geo geo, int64_t fs_in,
                                                           int64_t fs_out, int nf) {
     __shared__ cx<T> sm[tile_lds<T, CF, CF::G * CF::TL>()];
-    ypass_body<T, CF, CF::G * CF::TL, INV>(in, out, tw, geo, fs_in, fs_out, nf, blockIdx.x, threadIdx.x, sm);
+    // FP64: each XCD takes a contiguous range of tiles (measured 10% faster; FP32 slightly slower)
+    ypass_body<T, CF, CF::G * CF::TL, INV>(in, out, tw, geo, fs_in, fs_out, nf,
+                                           sizeof(T) == 8 ? xcd_unit() : (int64_t)blockIdx.x, threadIdx.x, sm);
 }
 
 // ------------------------------------------------------------ fused x pass
@@ -313,7 +323,9 @@ template <typename T, class CF, bool MHD>
 __global__ __launch_bounds__((CF::G * CF::TL)) void k_xpass(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
                                                           const cx<T>* __restrict__ tw, Geo geo) {
     __shared__ cx<T> sm[tile_lds<T, CF, CF::G * CF::TL>()];
-    xpass_body<T, CF, CF::G * CF::TL, MHD>(Bf, Cf, tw, geo, blockIdx.x, threadIdx.x, sm);
+    // each XCD takes a contiguous range of tiles (measured faster, most for the
+    // narrow MHD tiles at n = 1024 whose rows share cache lines)
+    xpass_body<T, CF, CF::G * CF::TL, MHD>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm);
 }
 
 // ------------------------------------------------------------ zfwd + update
