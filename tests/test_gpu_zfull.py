@@ -150,6 +150,36 @@ def test_mhd1024_invariants_and_dissipation(P, torch):
     torch.cuda.empty_cache()
 
 
+def test_mhd1024_taylor_green_closed_form(P, torch):
+    """The MHD right-hand side at 1024^3 (its x pass has its own radix schedule
+    there) for u = Taylor-Green, b = 0 and for u = 0, b = Taylor-Green: the
+    projected u x w (resp. j x b = -(b x curl b)) has a closed form, and the
+    induction term vanishes."""
+    n = N1024
+    m = 16
+    x = 2 * np.pi * np.arange(m) / m
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    Nx = np.stack([-np.sin(2 * X) * np.cos(2 * Z) / 8, -np.sin(2 * Y) * np.cos(2 * Z) / 8,
+                   (np.cos(2 * X) + np.cos(2 * Y)) * np.sin(2 * Z) / 8])
+    ref = embed(torch, np.stack([np.fft.rfftn(Nx[c], axes=(0, 1, 2)) / m ** 3 for c in range(3)]).astype(np.complex64),
+                n, 2)
+    tg = embed(torch, I.taylor_green_spec(m).astype(np.complex64), n, 1)
+    plan = P.Plan(n, solver="mhd", precision="fp32")
+    st = torch.zeros((6, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    rhs = torch.empty_like(st)
+    scale = ref.abs().max().item()
+    for part, sign in ((slice(0, 3), 1.0), (slice(3, 6), -1.0)):
+        st.zero_()
+        st[part] = tg
+        plan.rhs(st, rhs)
+        err_u = (rhs[:3] - sign * ref).abs().max().item()
+        err_b = rhs[3:].abs().max().item()
+        assert err_u < 1e-5 * scale and err_b < 1e-5 * scale, (part, err_u, err_b, scale)
+    plan.close()
+    del st, rhs, ref, tg
+    torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------------ ensemble, 96 runs
 def test_ensemble_96_runs(O, P, torch, tmp_path):
     sizes = [48] * 32 + [64] * 48 + [96] * 16
