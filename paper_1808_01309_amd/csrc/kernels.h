@@ -49,7 +49,18 @@ struct KCfg {
     using P = P_;
     static constexpr int N = P_::N, G = G_, TL = TL_;
 };
-template <typename T, int N> using LineCfg = KCfg<typename NCfg<N>::P, NCfg<N>::G, 1>;
+// z passes (one line per G threads): at n = 1024 a line is spread over 128
+// threads (8 points each, radices 8 8 4 4) so that the curl / projection / RK
+// bodies stay within a register budget that lets several wavefronts share a SIMD.
+template <int N> struct LPlan {
+    using P = typename NCfg<N>::P;
+    static constexpr int G = NCfg<N>::G;
+};
+template <> struct LPlan<1024> {
+    using P = Radices<8, 8, 4, 4>;
+    static constexpr int G = 128;
+};
+template <typename T, int N> using LineCfg = KCfg<typename LPlan<N>::P, LPlan<N>::G, 1>;
 template <typename T, int N> using TileCfg = KCfg<typename NCfg<N>::P, NCfg<N>::G, tile_lines<T>()>;
 // The x pass holds every field of its lines in registers until the products
 // are formed; for MHD at n = 1024 (12 fields) it spreads a line over 128
@@ -119,7 +130,7 @@ __device__ __forceinline__ void zinv_body(const cx<T>* __restrict__ st, cx<T>* _
     // A line's G threads are lanes of one wavefront: the FP64 transforms
     // synchronise per wavefront (measured faster there; FP32 keeps the
     // workgroup barrier, which measured slightly faster for it).
-    using F = Fft<T, typename CF::P, G, true, false, sizeof(T) == 8>;
+    using F = Fft<T, typename CF::P, G, true, false, sizeof(T) == 8 && G <= 64>;
     constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
     const int l = tid / G, g = tid % G;
     const int64_t line = unit * LPB + l;

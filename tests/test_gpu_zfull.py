@@ -150,11 +150,12 @@ def test_mhd1024_invariants_and_dissipation(P, torch):
     torch.cuda.empty_cache()
 
 
-def test_mhd1024_taylor_green_closed_form(P, torch):
-    """The MHD right-hand side at 1024^3 (its x pass has its own radix schedule
-    there) for u = Taylor-Green, b = 0 and for u = 0, b = Taylor-Green: the
-    projected u x w (resp. j x b = -(b x curl b)) has a closed form, and the
-    induction term vanishes."""
+def test_1024_taylor_green_closed_form(P, torch):
+    """Right-hand sides at 1024^3 (where the x pass of MHD and the z passes have
+    their own radix schedules): MHD for u = Taylor-Green, b = 0 and for u = 0,
+    b = Taylor-Green, where the projected u x w (resp. j x b = -(b x curl b))
+    has a closed form and the induction term vanishes; Navier-Stokes (FP32,
+    FP64) for u = Taylor-Green."""
     n = N1024
     m = 16
     x = 2 * np.pi * np.arange(m) / m
@@ -176,8 +177,20 @@ def test_mhd1024_taylor_green_closed_form(P, torch):
         err_b = rhs[3:].abs().max().item()
         assert err_u < 1e-5 * scale and err_b < 1e-5 * scale, (part, err_u, err_b, scale)
     plan.close()
-    del st, rhs, ref, tg
+    del st, rhs
     torch.cuda.empty_cache()
+    # the Navier-Stokes path at the same size (its z passes share the schedule)
+    for prec, ct in (("fp32", torch.complex64), ("fp64", torch.complex128)):
+        plan = P.Plan(n, precision=prec)
+        su = tg.to(ct)
+        rhs = torch.empty_like(su)
+        plan.rhs(su, rhs)
+        err = (rhs - ref.to(ct)).abs().max().item()
+        assert err < (1e-5 if prec == "fp32" else 1e-12) * scale, (prec, err, scale)
+        plan.close()
+        del su, rhs
+        torch.cuda.empty_cache()
+    del ref, tg
 
 
 # ------------------------------------------------------------ ensemble, 96 runs
