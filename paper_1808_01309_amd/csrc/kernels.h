@@ -353,12 +353,12 @@ __global__ __launch_bounds__((CF::G * CF::TL)) void k_xpass(const cx<T>* __restr
 
 // ------------------------------------------------------------ zfwd + update
 template <typename T>
-__device__ __forceinline__ void rk_apply(int mode, const RkArgs<T>& a, int grp, int64_t idx, int k2, cx<T> nk) {
+__device__ __forceinline__ void rk_apply(int mode, const RkArgs<T>& a, int64_t idx, T E, T E2, cx<T> nk) {
     if (mode == Z_RHS) {
         a.R[idx] = nk;
         return;
     }
-    const T E = a.E[grp][k2], E2 = a.E2[grp][k2], h = a.h;
+    const T h = a.h;
     switch (mode) {
         case Z_RK4_0: {
             const cx<T> un = a.U[idx];
@@ -450,8 +450,11 @@ __device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<
             for (int c = 0; c < 3; ++c) o[c] = cadd(o[c], ra.F[c * fs + fi]);
         }
         if (ra.lin_only) o[0] = o[1] = o[2] = czero<T>();
+        // integrating factors by |k|^2, loaded once per mode for all components
+        // (the stage-array stores in between would otherwise force reloads)
+        const T Eu = ra.E[0][k2], E2u = ra.E2[0][k2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rk_apply(mode, ra, 0, c * geo.sc + idx, k2, o[c]);
+        for (int c = 0; c < 3; ++c) rk_apply(mode, ra, c * geo.sc + idx, Eu, E2u, o[c]);
         if constexpr (MHD) {
             // b: i k x F[u x b]
             const cx<T> m0 = cscale(v[3][e], scale), m1 = cscale(v[4][e], scale), m2 = cscale(v[5][e], scale);
@@ -460,8 +463,9 @@ __device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<
             b[1] = mul_i(cx<T>{fkz * m0.x - fkx * m2.x, fkz * m0.y - fkx * m2.y});
             b[2] = mul_i(cx<T>{fkx * m1.x - fky * m0.x, fkx * m1.y - fky * m0.y});
             if (ra.lin_only || cut) b[0] = b[1] = b[2] = czero<T>();
+            const T Eb = ra.E[1][k2], E2b = ra.E2[1][k2];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) rk_apply(mode, ra, 1, (3 + c) * geo.sc + idx, k2, b[c]);
+            for (int c = 0; c < 3; ++c) rk_apply(mode, ra, (3 + c) * geo.sc + idx, Eb, E2b, b[c]);
         }
     }
 }
