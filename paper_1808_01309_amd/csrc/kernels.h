@@ -352,49 +352,54 @@ __global__ __launch_bounds__((CF::G * CF::TL)) void k_xpass(const cx<T>* __restr
 }
 
 // ------------------------------------------------------------ zfwd + update
+// The stage arrays are distinct buffers: restrict-qualified here and in
+// zfwd_lines so that loads of later modes may be issued ahead of earlier stores.
 template <typename T>
-__device__ __forceinline__ void rk_apply(int mode, const RkArgs<T>& a, int64_t idx, T E, T E2, cx<T> nk) {
+__device__ __forceinline__ void rk_apply(int mode, cx<T>* __restrict__ U, cx<T>* __restrict__ V,
+                                         cx<T>* __restrict__ Acc, cx<T>* __restrict__ R, T h, int64_t idx, T E, T E2,
+                                         cx<T> nk) {
     if (mode == Z_RHS) {
-        a.R[idx] = nk;
+        R[idx] = nk;
         return;
     }
-    const T h = a.h;
     switch (mode) {
         case Z_RK4_0: {
-            const cx<T> un = a.U[idx];
-            a.V[idx] = {E * (un.x + T(0.5) * h * nk.x), E * (un.y + T(0.5) * h * nk.y)};
-            a.Acc[idx] = {E2 * (un.x + (h / T(6)) * nk.x), E2 * (un.y + (h / T(6)) * nk.y)};
+            const cx<T> un = U[idx];
+            V[idx] = {E * (un.x + T(0.5) * h * nk.x), E * (un.y + T(0.5) * h * nk.y)};
+            Acc[idx] = {E2 * (un.x + (h / T(6)) * nk.x), E2 * (un.y + (h / T(6)) * nk.y)};
         } break;
         case Z_RK4_1: {
-            const cx<T> un = a.U[idx], ac = a.Acc[idx];
-            a.V[idx] = {E * un.x + T(0.5) * h * nk.x, E * un.y + T(0.5) * h * nk.y};
-            a.Acc[idx] = {ac.x + (h / T(3)) * E * nk.x, ac.y + (h / T(3)) * E * nk.y};
+            const cx<T> un = U[idx], ac = Acc[idx];
+            V[idx] = {E * un.x + T(0.5) * h * nk.x, E * un.y + T(0.5) * h * nk.y};
+            Acc[idx] = {ac.x + (h / T(3)) * E * nk.x, ac.y + (h / T(3)) * E * nk.y};
         } break;
         case Z_RK4_2: {
-            const cx<T> un = a.U[idx], ac = a.Acc[idx];
-            a.V[idx] = {E2 * un.x + h * E * nk.x, E2 * un.y + h * E * nk.y};
-            a.Acc[idx] = {ac.x + (h / T(3)) * E * nk.x, ac.y + (h / T(3)) * E * nk.y};
+            const cx<T> un = U[idx], ac = Acc[idx];
+            V[idx] = {E2 * un.x + h * E * nk.x, E2 * un.y + h * E * nk.y};
+            Acc[idx] = {ac.x + (h / T(3)) * E * nk.x, ac.y + (h / T(3)) * E * nk.y};
         } break;
         case Z_RK4_3: {
-            const cx<T> ac = a.Acc[idx];
-            a.U[idx] = {ac.x + (h / T(6)) * nk.x, ac.y + (h / T(6)) * nk.y};
+            const cx<T> ac = Acc[idx];
+            U[idx] = {ac.x + (h / T(6)) * nk.x, ac.y + (h / T(6)) * nk.y};
         } break;
         case Z_RK2_0: {
-            const cx<T> un = a.U[idx];
-            a.V[idx] = {E2 * (un.x + h * nk.x), E2 * (un.y + h * nk.y)};
-            a.Acc[idx] = {E2 * (un.x + T(0.5) * h * nk.x), E2 * (un.y + T(0.5) * h * nk.y)};
+            const cx<T> un = U[idx];
+            V[idx] = {E2 * (un.x + h * nk.x), E2 * (un.y + h * nk.y)};
+            Acc[idx] = {E2 * (un.x + T(0.5) * h * nk.x), E2 * (un.y + T(0.5) * h * nk.y)};
         } break;
         case Z_RK2_1: {
-            const cx<T> ac = a.Acc[idx];
-            a.U[idx] = {ac.x + T(0.5) * h * nk.x, ac.y + T(0.5) * h * nk.y};
+            const cx<T> ac = Acc[idx];
+            U[idx] = {ac.x + T(0.5) * h * nk.x, ac.y + T(0.5) * h * nk.y};
         } break;
         default: break;
     }
 }
 
 template <typename T, class CF, int NT, bool MHD>
-__device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw, const Geo& geo,
-                                          const RkArgs<T>& ra, int mode, int64_t unit, int tid, cx<T>* sm) {
+__device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw, const Geo& geo,
+                                           const RkArgs<T>& ra, cx<T>* __restrict__ U, cx<T>* __restrict__ V,
+                                           cx<T>* __restrict__ Acc, cx<T>* __restrict__ R, int mode, int64_t unit,
+                                           int tid, cx<T>* sm) {
     constexpr int N = CF::N, G = CF::G;
     using F = Fft<T, typename CF::P, G, false>;
     constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
@@ -454,7 +459,7 @@ __device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<
         // (the stage-array stores in between would otherwise force reloads)
         const T Eu = ra.E[0][k2], E2u = ra.E2[0][k2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) rk_apply(mode, ra, c * geo.sc + idx, Eu, E2u, o[c]);
+        for (int c = 0; c < 3; ++c) rk_apply(mode, U, V, Acc, R, ra.h, c * geo.sc + idx, Eu, E2u, o[c]);
         if constexpr (MHD) {
             // b: i k x F[u x b]
             const cx<T> m0 = cscale(v[3][e], scale), m1 = cscale(v[4][e], scale), m2 = cscale(v[5][e], scale);
@@ -465,9 +470,15 @@ __device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<
             if (ra.lin_only || cut) b[0] = b[1] = b[2] = czero<T>();
             const T Eb = ra.E[1][k2], E2b = ra.E2[1][k2];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) rk_apply(mode, ra, (3 + c) * geo.sc + idx, Eb, E2b, b[c]);
+            for (int c = 0; c < 3; ++c) rk_apply(mode, U, V, Acc, R, ra.h, (3 + c) * geo.sc + idx, Eb, E2b, b[c]);
         }
     }
+}
+
+template <typename T, class CF, int NT, bool MHD>
+__device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw, const Geo& geo,
+                                          const RkArgs<T>& ra, int mode, int64_t unit, int tid, cx<T>* sm) {
+    zfwd_lines<T, CF, NT, MHD>(D, tw, geo, ra, ra.U, ra.V, ra.Acc, ra.R, mode, unit, tid, sm);
 }
 
 template <typename T, class CF, bool MHD>
