@@ -208,8 +208,11 @@ struct Fft {
         return g + (e / R_LAST) * G + (e % R_LAST) * (N / R_LAST);
     }
 
-    template <int s, class Lds>
-    __device__ __forceinline__ static void stage(cx<T> (&v)[E], int g, const Lds& lds, const cx<T>* __restrict__ tw) {
+    static constexpr int EXCH = S - 1;   // LDS exchanges per transform
+
+    template <int s, bool PP, class Lds>
+    __device__ __forceinline__ static void stage(cx<T> (&v)[E], int g, const Lds& l0, const Lds& l1, int ex,
+                                                 const cx<T>* __restrict__ tw) {
         constexpr int R = radix_at<P, REV>(s);
         constexpr int NS = span_at<P, REV>(s);
         constexpr int NB = E / R;
@@ -229,6 +232,7 @@ struct Fft {
             dft<R, INV>(&v[i * R]);
         }
         if constexpr (s + 1 < S) {
+            const Lds lds = (PP && ((ex + s) & 1)) ? l1 : l0;
             constexpr int R2 = radix_at<P, REV>(s + 1);
             constexpr int NB2 = E / R2;
 #pragma unroll
@@ -243,14 +247,27 @@ struct Fft {
             for (int i = 0; i < NB2; ++i)
 #pragma unroll
                 for (int r = 0; r < R2; ++r) v[i * R2 + r] = lds(g + i * G + r * (N / R2));
-            lds_sync<WS>();
-            stage<s + 1>(v, g, lds, tw);
+            if constexpr (!PP) lds_sync<WS>();
+            stage<s + 1, PP>(v, g, l0, l1, ex, tw);
         }
     }
 
     template <class Lds>
     __device__ __forceinline__ static void run(cx<T> (&v)[E], int g, const Lds& lds, const cx<T>* __restrict__ tw) {
-        stage<0>(v, g, lds, tw);
+        stage<0, false>(v, g, lds, lds, 0, tw);
+    }
+
+    // Ping-pong form: exchange x of this transform goes through view
+    // (ex + x) & 1 of two disjoint LDS buffers, with one barrier between its
+    // writes and its reads and none after them.  This is safe when the
+    // caller's LDS phases (each: writes, one barrier, reads) strictly alternate
+    // between the two buffers: a buffer is rewritten only after the barrier of
+    // the phase in between, which every reader of its old contents has passed.
+    // The caller continues with phase number ex + EXCH.
+    template <class Lds>
+    __device__ __forceinline__ static void run_pp(cx<T> (&v)[E], int g, const Lds& l0, const Lds& l1, int ex,
+                                                  const cx<T>* __restrict__ tw) {
+        stage<0, true>(v, g, l0, l1, ex, tw);
     }
 };
 

@@ -244,7 +244,7 @@ __global__ __launch_bounds__((CF::G * CF::TL)) void k_ypass(const cx<T>* __restr
 // (v, i k x v) packed as one complex line each (two real transforms for the
 // price of one), cross products in registers, forward x of the products
 // packed two per complex line, split by Hermitian symmetry, kx <= K kept.
-template <typename T, class CF, int NT, bool MHD>
+template <typename T, class CF, int NT, bool MHD, bool PPB = false>
 __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
                                            const cx<T>* __restrict__ tw, const Geo& geo, int64_t unit, int tid,
                                            cx<T>* sm) {
@@ -263,7 +263,13 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     const int y = valid ? (int)(tile / NTZ) : 0;
     const int z = zt * TL + t;
     const bool zin = valid && z < N;
+    // PPB: two LDS buffers of the block's tiles, used by alternate phases
+    // (staging of a pair, transform exchanges, output staging), so that each
+    // phase needs a single barrier (see Fft::run_pp).
+    constexpr int TSZ = SG * N * TLP;
     const TileLds<T, TLP> lds{sm + s * N * TLP + t};
+    const TileLds<T, TLP> lds1{sm + (PPB ? TSZ : 0) + s * N * TLP + t};
+    int ex = 0;   // LDS phases so far
     const int64_t nn = (int64_t)N * N;
     const int64_t off = (int64_t)y * N + z;
     const int K = geo.K;
@@ -271,9 +277,10 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     // LDS (coalesced along z); the packed line Z = V + i W and its Hermitian
     // mirror Z(N - kx) = conj V + i conj W are then assembled from LDS.
     cx<T> v[NP][E];
-    cx<T>* const stage = sm + s * N * TLP;   // this tile's LDS (2 (K+1) TLP <= N TLP)
 #pragma unroll
     for (int pi = 0; pi < NP; ++pi) {
+        // this tile's LDS (2 (K+1) TLP <= N TLP)
+        cx<T>* const stage = sm + ((PPB && (ex & 1)) ? TSZ : 0) + s * N * TLP;
         const int fu = (pi / 3) * 6 + pi % 3, fw = fu + 3;
         for (int kx = g; kx <= K; kx += G) {
             stage[kx * TLP + t] = zin ? Bf[fu * geo.sb + kx * nn + off] : czero<T>();
@@ -295,10 +302,18 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
             }
             v[pi][e] = Z;
         }
-        __syncthreads();
+        if constexpr (!PPB) __syncthreads();
+        ++ex;
     }
 #pragma unroll
-    for (int pi = 0; pi < NP; ++pi) FI::run(v[pi], g, lds, tw);
+    for (int pi = 0; pi < NP; ++pi) {
+        if constexpr (PPB) {
+            FI::run_pp(v[pi], g, lds, lds1, ex, tw);
+            ex += FI::EXCH;
+        } else {
+            FI::run(v[pi], g, lds, tw);
+        }
+    }
     // physical space: Re = v, Im = curl v at x = last_pos(g, e)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -322,14 +337,20 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     }
 #pragma unroll
     for (int po = 0; po < NO; ++po) {
-        FF::run(v[po], g, lds, tw);
+        if constexpr (PPB) {
+            FF::run_pp(v[po], g, lds, lds1, ex, tw);
+            ex += FF::EXCH;
+        } else {
+            FF::run(v[po], g, lds, tw);
+        }
+        const TileLds<T, TLP> lo = (PPB && (ex & 1)) ? lds1 : lds;
 #pragma unroll
-        for (int e = 0; e < E; ++e) lds(FF::last_pos(g, e)) = v[po][e];
+        for (int e = 0; e < E; ++e) lo(FF::last_pos(g, e)) = v[po][e];
         __syncthreads();
         if (zin) {
             const int fa = 2 * po, fb = 2 * po + 1;
             for (int kx = g; kx <= K; kx += G) {
-                const cx<T> a = lds(kx), b = lds(kx == 0 ? 0 : N - kx);
+                const cx<T> a = lo(kx), b = lo(kx == 0 ? 0 : N - kx);
                 const cx<T> A = {T(0.5) * (a.x + b.x), T(0.5) * (a.y - b.y)};
                 Cf[fa * geo.sb + kx * nn + off] = A;
                 if (fb < NOUT) {
@@ -338,17 +359,25 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
                 }
             }
         }
-        __syncthreads();
+        if constexpr (!PPB) __syncthreads();
+        ++ex;
     }
+}
+
+// Two tile buffers for Navier-Stokes where they fit in the 160 KB of LDS of
+// a CU (for MHD the alternating views cost registers, and occupancy at 1024).
+template <typename T, class CF, bool MHD> constexpr bool xpass_pp() {
+    return !MHD && 2 * tile_lds<T, CF, CF::G * CF::TL>() * (int)sizeof(cx<T>) <= 160 * 1024;
 }
 
 template <typename T, class CF, bool MHD>
 __global__ __launch_bounds__((CF::G * CF::TL)) void k_xpass(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
                                                           const cx<T>* __restrict__ tw, Geo geo) {
-    __shared__ cx<T> sm[tile_lds<T, CF, CF::G * CF::TL>()];
+    constexpr bool PPB = xpass_pp<T, CF, MHD>();
+    __shared__ cx<T> sm[(PPB ? 2 : 1) * tile_lds<T, CF, CF::G * CF::TL>()];
     // each XCD takes a contiguous range of tiles (measured faster, most for the
     // narrow MHD tiles at n = 1024 whose rows share cache lines)
-    xpass_body<T, CF, CF::G * CF::TL, MHD>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm);
+    xpass_body<T, CF, CF::G * CF::TL, MHD, PPB>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm);
 }
 
 // ------------------------------------------------------------ zfwd + update
