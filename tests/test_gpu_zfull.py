@@ -10,6 +10,10 @@ benchmark times (collected after the other GPU tests: these are the slow ones).
   dealiased nonlinear terms conserve total energy and cross-helicity exactly,
   so their transfers must vanish to rounding; over 5 steps the total energy
   must fall by the dissipation alone.
+* MHD at 128^3 and 256^3 (the sizes below 1024^3 where the oracle still fits
+  in host memory): right-hand side of the FP32 and FP64 paths against the
+  oracle, and one RK2 step of the 1024^3 benchmark's parameters at 128^3; the
+  Navier-Stokes right-hand side at 256^3 (its own radix schedule).
 * The 96-run ensemble (32 x 48^3, 48 x 64^3, 16 x 96^3) with its autotuned
   schedule: the graph-replayed persistent step equals the batched launches
   bitwise for every run, and one run of each size equals the oracle.
@@ -191,6 +195,70 @@ def test_1024_taylor_green_closed_form(P, torch):
         del su, rhs
         torch.cuda.empty_cache()
     del ref, tg
+
+
+# ------------------------------------------------------------ 128^3, 256^3
+_mid = {}
+
+
+def mhd_case(O, n):
+    """Inputs and oracle right-hand side of the MHD case at n (cached per n)."""
+    if ("mhd", n) not in _mid:
+        kw = dict(spectrum=I.spectrum_c3, energy=0.5)
+        u = I.random_solenoidal(n, 40 + n, **kw)
+        b = I.random_solenoidal(n, 40 + n, field=1, **kw)
+        _mid[("mhd", n)] = (u, b) + tuple(O.mhd_rhs(u, b))
+    return _mid[("mhd", n)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("n", [128, 256])
+def test_mhd_rhs_mid_sizes(O, P, torch, n, prec):
+    u, b, ru, rb = mhd_case(O, n)
+    plan = P.Plan(n, solver="mhd", precision=prec)
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    sd = torch.from_numpy(np.concatenate([u, b])).to(ct).cuda()
+    rd = torch.empty_like(sd)
+    plan.rhs(sd, rd)
+    got = rd.cpu().numpy()
+    assert max(rel(got[c], ru[c]) for c in range(3)) < TOL[prec]
+    assert max(rel(got[3 + c], rb[c]) for c in range(3)) < TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_mhd_step_128(O, P, torch, prec):
+    n, nu, dt = 128, 1e-3, 2.5e-4
+    u, b = mhd_case(O, n)[:2]
+    if ("mhd_step", n) not in _mid:
+        _mid[("mhd_step", n)] = O.step(u, 1, dt=dt, nu=nu, eta=nu, rk=2, bhat=b)
+    su, sb = _mid[("mhd_step", n)]
+    plan = P.Plan(n, solver="mhd", precision=prec, rk_order=2, nu=nu, eta=nu, dt=dt)
+    plan.set_state(u, field="u")
+    plan.set_state(b, field="b")
+    plan.step(1)
+    assert max(rel(plan.get_state("u")[c], su[c]) for c in range(3)) < TOL[prec]
+    assert max(rel(plan.get_state("b")[c], sb[c]) for c in range(3)) < TOL[prec]
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_ns_rhs_256(O, P, torch, prec):
+    n = 256
+    if ("ns", n) not in _mid:
+        u = I.random_solenoidal(n, 10 + n)
+        f = I.forcing_shells(n, 10 + n)
+        _mid[("ns", n)] = (u, f, O.ns_rhs(u, f))
+    u, f, ref = _mid[("ns", n)]
+    plan = P.Plan(n, precision=prec)
+    plan.set_forcing(f)
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    sd = torch.from_numpy(u).to(ct).cuda()
+    rd = torch.empty_like(sd)
+    plan.rhs(sd, rd)
+    got = rd.cpu().numpy()
+    assert max(rel(got[c], ref[c]) for c in range(3)) < TOL[prec]
+    plan.close()
 
 
 # ------------------------------------------------------------ ensemble, 96 runs
