@@ -1,4 +1,4 @@
-"""Plain FP64 CPU oracle for the pseudospectral Navier-Stokes / MHD hot path.
+"""Plain FP64 CPU oracle for the pseudospectral Navier-Stokes / MHD / Boussinesq hot path.
 
 TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
 leg of the benchmark may import this package; the product library never does.
@@ -34,6 +34,7 @@ class OraParams(ctypes.Structure):
         ("nu", ctypes.c_double),
         ("eta", ctypes.c_double),
         ("dt", ctypes.c_double),
+        ("nbv", ctypes.c_double),
     ]
 
 
@@ -52,6 +53,9 @@ def lib():
         L.ora_c2c3.argtypes = [i, i, i, P, i]
         L.ora_ns_rhs.argtypes = [i, i, i, P, P, P]
         L.ora_mhd_rhs.argtypes = [i, i, i, P, P, P, P]
+        L.ora_bq_rhs.argtypes = [i, i, i, ctypes.c_double, P, P, P, P, P]
+        L.ora_energy_nc.argtypes = [i, i, P]
+        L.ora_energy_nc.restype = ctypes.c_double
         L.ora_step.argtypes = [ctypes.POINTER(OraParams), P, P, P, i]
         L.ora_step.restype = i
         L.ora_energy.argtypes = [i, P]
@@ -153,15 +157,36 @@ def mhd_rhs(uhat, bhat, kcut=None, sphere=False):
     return ou, ob
 
 
+def bq_rhs(uhat, thhat, nbv, fhat=None, kcut=None, sphere=False):
+    """Boussinesq operators (N_u, N_theta); thhat is [n][n][n//2+1] (or [1][...])."""
+    uhat = _c128(uhat)
+    th = _c128(thhat).reshape(uhat.shape[1:])
+    n = uhat.shape[1]
+    if kcut is None:
+        kcut = kcut_23(n)
+    ou = np.empty_like(uhat)
+    ot = np.empty_like(th)
+    f = _c128(fhat) if fhat is not None else None
+    lib().ora_bq_rhs(n, kcut, int(sphere), float(nbv), _ptr(uhat), _ptr(th),
+                     _ptr(f) if f is not None else None, _ptr(ou), _ptr(ot))
+    return ou, ot
+
+
 def step(uhat, nsteps, *, dt, nu, rk=4, bhat=None, eta=None, fhat=None, kcut=None,
-         sphere=False, linear_only=False):
-    """Advance (u, b) by nsteps Lawson IF-RK steps; returns new arrays."""
+         sphere=False, linear_only=False, theta=None, kappa=None, nbv=0.0):
+    """Advance (u, b) or (u, theta) by nsteps Lawson IF-RK steps; returns new
+    arrays.  theta (Boussinesq): [n][n][n//2+1], diffusivity kappa (default nu)."""
     u = _c128(uhat).copy()
     n = u.shape[1]
-    b = _c128(bhat).copy() if bhat is not None else None
-    p = OraParams(n=n, solver=1 if b is not None else 0, rk_order=rk,
+    if theta is not None:
+        b = _c128(theta).reshape(u.shape[1:]).copy()
+        solver, e2 = 2, nu if kappa is None else kappa
+    else:
+        b = _c128(bhat).copy() if bhat is not None else None
+        solver, e2 = (1 if b is not None else 0), nu if eta is None else eta
+    p = OraParams(n=n, solver=solver, rk_order=rk,
                   kcut=kcut_23(n) if kcut is None else kcut, sphere=int(sphere),
-                  linear_only=int(linear_only), nu=nu, eta=nu if eta is None else eta, dt=dt)
+                  linear_only=int(linear_only), nu=nu, eta=e2, dt=dt, nbv=float(nbv))
     f = _c128(fhat) if fhat is not None else None
     lib().ora_step(ctypes.byref(p), _ptr(u), _ptr(b) if b is not None else None,
                    _ptr(f) if f is not None else None, nsteps)
@@ -169,8 +194,12 @@ def step(uhat, nsteps, *, dt, nu, rk=4, bhat=None, eta=None, fhat=None, kcut=Non
 
 
 def energy(vhat):
+    """1/2 sum_k w |vhat|^2 over the components of a [3][n][n][n//2+1] field, or
+    of a scalar field given as [n][n][n//2+1] or [1][n][n][n//2+1]."""
     vhat = _c128(vhat)
-    return lib().ora_energy(vhat.shape[1], _ptr(vhat))
+    if vhat.ndim == 3:
+        vhat = vhat[None]
+    return lib().ora_energy_nc(vhat.shape[1], vhat.shape[0], _ptr(vhat))
 
 
 def enstrophy(vhat):

@@ -20,7 +20,8 @@
  *     projection onto divergence-free fields: Sec. 2, paragraph after
  *     eq. (fftsum);
  *   - the incompressible Navier-Stokes equations (eq. mom + eq. divv with
- *     theta = 0) and MHD (eq. uMHD, eq. bMHD);
+ *     theta = 0), MHD (eq. uMHD, eq. bMHD) and the Boussinesq equations
+ *     (eq. mom, eq. temp, eq. divv);
  *   - explicit Runge-Kutta time stepping of order 2-4: Sec. 2.
  *
  * Readings where the paper is silent (normalisation, dealiasing rule,
@@ -394,18 +395,71 @@ void ora_mhd_rhs(int n, int kcut, int sphere, const double *uhat, const double *
     free(tmp); free(ur); free(br); free(qr); free(nr);
 }
 
+/* Boussinesq operators (eq. mom with its buoyancy term, eq. temp, eq. divv).
+ * Momentum in rotational form (the gradient part of u . grad u joins the
+ * pressure and is removed by the projection); the scalar in advective form:
+ *   N_u = D P (F[u x w] - nbv theta zhat) + f,
+ *   N_t = D (-F[u . grad theta] + nbv w_z),
+ * with w = i k x uhat, grad theta = c2r(i k thetahat) and w_z the z component
+ * of the velocity coefficients.  thhat, out_t: [n][n][n/2+1] complex.        */
+void ora_bq_rhs(int n, int kcut, int sphere, double nbv, const double *uhat, const double *thhat,
+                const double *fhat, double *out_u, double *out_t)
+{
+    long nh = NH(n), np = (long)n * n * n;
+    int nxh = n / 2 + 1;
+    const cplx *u = (const cplx *)uhat, *th = (const cplx *)thhat;
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nh);
+    double *ur = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    double *qr = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    double *nr = (double *)malloc(sizeof(double) * 3 * (size_t)np);
+    cplx *ou = (cplx *)out_u, *ot = (cplx *)out_t;
+    c2r_vec(n, u, ur);
+    spectral_curl(n, u, tmp);
+    c2r_vec(n, tmp, qr);           /* w */
+    cross(np, ur, qr, nr, 0);      /* u x w */
+    r2c_vec(n, nr, ou);
+    for (long i = 0; i < nh; ++i) ou[2 * nh + i] -= nbv * th[i];   /* buoyancy */
+    dealias_project(n, ou, (const cplx *)fhat, kcut, sphere);
+    /* grad theta = i k thetahat, then u . grad theta in physical space */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < nxh; ++x) {
+                long i = IDX(n, z, y, x);
+                double kx = x, ky = wn(y, n), kz = wn(z, n);
+                tmp[i] = I * kx * th[i];
+                tmp[nh + i] = I * ky * th[i];
+                tmp[2 * nh + i] = I * kz * th[i];
+            }
+    c2r_vec(n, tmp, qr);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < np; ++i)
+        nr[i] = -(ur[i] * qr[i] + ur[np + i] * qr[np + i] + ur[2 * np + i] * qr[2 * np + i]);
+    ora_r2c3(n, n, n, nr, out_t);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int z = 0; z < n; ++z)
+        for (int y = 0; y < n; ++y)
+            for (int x = 0; x < nxh; ++x) {
+                long i = IDX(n, z, y, x);
+                if (kept(x, wn(y, n), wn(z, n), kcut, sphere)) ot[i] += nbv * u[2 * nh + i];
+                else ot[i] = 0;
+            }
+    free(tmp); free(ur); free(qr); free(nr);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Time stepping: Lawson integrating factor + explicit Runge-Kutta            */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
     int n;
-    int solver;      /* 0 = Navier-Stokes, 1 = MHD */
+    int solver;      /* 0 = Navier-Stokes, 1 = MHD, 2 = Boussinesq */
     int rk_order;    /* 2 (Heun) or 4 (classical) */
     int kcut;        /* dealias cutoff K (< 0: none) */
     int sphere;      /* 0 = cube truncation, 1 = sphere */
     int linear_only; /* 1: nonlinear operator replaced by zero */
-    double nu, eta, dt;
+    double nu, eta, dt;   /* eta: magnetic (MHD) or scalar (Boussinesq) diffusivity */
+    double nbv;           /* Brunt-Vaisala frequency (Boussinesq) */
 } ora_params;
 
 /* Evaluate the nonlinear operator(s) for the state (u, b) into (ku, kb). */
@@ -415,14 +469,17 @@ static void eval_rhs(const ora_params *p, const cplx *u, const cplx *b, const cp
     long nh = NH(p->n);
     if (p->linear_only) {
         memset(ku, 0, sizeof(cplx) * 3 * (size_t)nh);
-        if (p->solver == 1) memset(kb, 0, sizeof(cplx) * 3 * (size_t)nh);
+        if (p->solver != 0) memset(kb, 0, sizeof(cplx) * (p->solver == 2 ? 1 : 3) * (size_t)nh);
         return;
     }
     if (p->solver == 0)
         ora_ns_rhs(p->n, p->kcut, p->sphere, (const double *)u, (const double *)f, (double *)ku);
-    else
+    else if (p->solver == 1)
         ora_mhd_rhs(p->n, p->kcut, p->sphere, (const double *)u, (const double *)b,
                     (double *)ku, (double *)kb);
+    else
+        ora_bq_rhs(p->n, p->kcut, p->sphere, p->nbv, (const double *)u, (const double *)b,
+                   (const double *)f, (double *)ku, (double *)kb);
 }
 
 /* Integrating factor per mode: E(k) = exp(-visc |k|^2 h / 2). */
@@ -440,8 +497,10 @@ static void if_table(int n, double visc, double h, double *E)
 }
 
 /* One Lawson step for one field group given the already evaluated stages is
- * not separable from the others (the operator couples u and b), so the step
- * below runs the stage loop over all fields together.  Stage formulas:
+ * not separable from the others (the operator couples u with b or theta), so
+ * the step below runs the stage loop over all fields together.  The second
+ * group is b (3 components, diffusivity eta) or theta (1 component, eta read
+ * as the scalar diffusivity kappa).  Stage formulas:
  *   RK2 (Heun):  k1 = N(u);  k2 = N(E^2 (u + h k1));
  *                u+ = E^2 u + h/2 (E^2 k1 + k2)
  *   RK4:         k1 = N(u);  k2 = N(E (u + h/2 k1));  k3 = N(E u + h/2 k2);
@@ -449,14 +508,16 @@ static void if_table(int n, double visc, double h, double *E)
  *                u+ = E^2 u + h/6 (E^2 k1 + 2 E (k2 + k3) + k4)              */
 int ora_step(const ora_params *p, double *uhat, double *bhat, const double *fhat, int nsteps)
 {
-    int n = p->n, mhd = p->solver == 1;
-    long nh = NH(n), tot = 3 * nh;
-    int nf = mhd ? 2 : 1;               /* field groups: u (and b) */
+    int n = p->n, two = p->solver != 0;
+    long nh = NH(n);
+    long tots[2] = {3 * nh, (p->solver == 2 ? 1 : 3) * nh};
+    int nf = two ? 2 : 1;               /* field groups: u (and b or theta) */
     double h = p->dt;
-    cplx *st[2] = {(cplx *)uhat, mhd ? (cplx *)bhat : NULL};
+    cplx *st[2] = {(cplx *)uhat, two ? (cplx *)bhat : NULL};
     double *E[2];
     cplx *k1[2], *k2[2], *k3[2], *k4[2], *v[2];
     for (int g = 0; g < nf; ++g) {
+        long tot = tots[g];
         E[g] = (double *)malloc(sizeof(double) * (size_t)nh);
         if_table(n, g == 0 ? p->nu : p->eta, h, E[g]);
         k1[g] = (cplx *)malloc(sizeof(cplx) * (size_t)tot);
@@ -465,7 +526,7 @@ int ora_step(const ora_params *p, double *uhat, double *bhat, const double *fhat
         k4[g] = (cplx *)malloc(sizeof(cplx) * (size_t)tot);
         v[g] = (cplx *)malloc(sizeof(cplx) * (size_t)tot);
     }
-    if (!mhd) { k1[1] = k2[1] = k3[1] = k4[1] = v[1] = NULL; }
+    if (!two) { k1[1] = k2[1] = k3[1] = k4[1] = v[1] = NULL; }
     const cplx *f = (const cplx *)fhat;
 
     for (int s = 0; s < nsteps; ++s) {
@@ -473,14 +534,14 @@ int ora_step(const ora_params *p, double *uhat, double *bhat, const double *fhat
             eval_rhs(p, st[0], st[1], f, k1[0], k1[1]);
             for (int g = 0; g < nf; ++g)
 #pragma omp parallel for schedule(static)
-                for (long i = 0; i < tot; ++i) {
+                for (long i = 0; i < tots[g]; ++i) {
                     double e2 = E[g][i % nh] * E[g][i % nh];
                     v[g][i] = e2 * (st[g][i] + h * k1[g][i]);
                 }
             eval_rhs(p, v[0], v[1], f, k2[0], k2[1]);
             for (int g = 0; g < nf; ++g)
 #pragma omp parallel for schedule(static)
-                for (long i = 0; i < tot; ++i) {
+                for (long i = 0; i < tots[g]; ++i) {
                     double e2 = E[g][i % nh] * E[g][i % nh];
                     st[g][i] = e2 * st[g][i] + 0.5 * h * (e2 * k1[g][i] + k2[g][i]);
                 }
@@ -488,24 +549,24 @@ int ora_step(const ora_params *p, double *uhat, double *bhat, const double *fhat
             eval_rhs(p, st[0], st[1], f, k1[0], k1[1]);
             for (int g = 0; g < nf; ++g)
 #pragma omp parallel for schedule(static)
-                for (long i = 0; i < tot; ++i)
+                for (long i = 0; i < tots[g]; ++i)
                     v[g][i] = E[g][i % nh] * (st[g][i] + 0.5 * h * k1[g][i]);
             eval_rhs(p, v[0], v[1], f, k2[0], k2[1]);
             for (int g = 0; g < nf; ++g)
 #pragma omp parallel for schedule(static)
-                for (long i = 0; i < tot; ++i)
+                for (long i = 0; i < tots[g]; ++i)
                     v[g][i] = E[g][i % nh] * st[g][i] + 0.5 * h * k2[g][i];
             eval_rhs(p, v[0], v[1], f, k3[0], k3[1]);
             for (int g = 0; g < nf; ++g)
 #pragma omp parallel for schedule(static)
-                for (long i = 0; i < tot; ++i) {
+                for (long i = 0; i < tots[g]; ++i) {
                     double e = E[g][i % nh];
                     v[g][i] = e * e * st[g][i] + h * e * k3[g][i];
                 }
             eval_rhs(p, v[0], v[1], f, k4[0], k4[1]);
             for (int g = 0; g < nf; ++g)
 #pragma omp parallel for schedule(static)
-                for (long i = 0; i < tot; ++i) {
+                for (long i = 0; i < tots[g]; ++i) {
                     double e = E[g][i % nh];
                     st[g][i] = e * e * st[g][i]
                              + h / 6.0 * (e * e * k1[g][i] + 2.0 * e * (k2[g][i] + k3[g][i]) + k4[g][i]);
@@ -539,8 +600,9 @@ static double pairwise(const double *a, long m)
     return pairwise(a, h) + pairwise(a + h, m - h);
 }
 
-/* Kinetic (or magnetic) energy E = 1/2 sum_k w |vhat|^2 = <|v|^2>/2. */
-double ora_energy(int n, const double *vhat)
+/* Energy of an nc-component field, E = 1/2 sum_k w |vhat|^2 = <|v|^2>/2
+ * (kinetic or magnetic energy for nc = 3, scalar variance for nc = 1).      */
+double ora_energy_nc(int n, int nc, const double *vhat)
 {
     long nh = NH(n);
     int nxh = n / 2 + 1;
@@ -550,7 +612,7 @@ double ora_energy(int n, const double *vhat)
     for (long i = 0; i < nh; ++i) {
         int x = (int)(i % nxh);
         double s = 0;
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < nc; ++c) {
             cplx z = v[c * nh + i];
             s += creal(z) * creal(z) + cimag(z) * cimag(z);
         }
@@ -560,6 +622,8 @@ double ora_energy(int n, const double *vhat)
     free(t);
     return e;
 }
+
+double ora_energy(int n, const double *vhat) { return ora_energy_nc(n, 3, vhat); }
 
 /* Enstrophy Z = 1/2 sum_k w |k|^2 |vhat(k)|^2 (the mean of |curl v|^2 / 2 for
  * a real field), pairwise-summed.                                            */

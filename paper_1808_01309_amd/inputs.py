@@ -151,6 +151,58 @@ def random_solenoidal(n, seed, field=0, spectrum=spectrum_c2, energy=1.0, kcut=N
     return out
 
 
+def random_scalar(n, seed, field=3, spectrum=spectrum_c2, energy=1.0, kcut=None, dtype=np.complex128):
+    """Random-phase real scalar field (temperature), spectral layout [n][n][n//2+1].
+
+    For every stored mode k != 0 inside the cube |k_i| <= kcut:
+        thetahat = A(|k|) exp(i t),  A = sqrt(E(|k|) / (4 pi |k|^2)),
+    t uniform in [0, 2 pi) from the counter-based generator (draw 0 of the
+    given field id), the kx = 0 plane Hermitian as in random_solenoidal, and
+    the amplitudes scaled to the variance 1/2 sum_k w |thetahat|^2 = energy.
+    """
+    if kcut is None:
+        kcut = kcut_23(n)
+    nxh = n // 2 + 1
+    out = np.zeros((n, n, nxh), dtype)
+    ks = np.arange(-kcut, kcut + 1)
+    kz2, ky2 = np.meshgrid(ks, ks, indexing="ij")
+    kz2, ky2 = kz2.ravel(), ky2.ravel()
+    planes = []
+    e_tot = 0.0
+    for kx in range(min(kcut, n // 2) + 1):
+        keep = ((ky2 > 0) | ((ky2 == 0) & (kz2 > 0))) if kx == 0 else np.ones(ky2.shape, bool)
+        ky, kz = ky2[keep], kz2[keep]
+        k2 = (kx * kx + ky * ky + kz * kz).astype(np.float64)
+        a2 = spectrum(np.sqrt(k2)) / (4.0 * np.pi * k2)
+        e_tot += float(np.sum(a2))
+        planes.append((kx, ky, kz, a2))
+    scale = energy / e_tot if e_tot > 0 else 0.0
+    for kx, ky, kz, a2 in planes:
+        t = 2.0 * np.pi * uniform(seed, field, np.full_like(ky, kx), ky, kz, 0)
+        coef = np.sqrt(a2 * scale) * np.exp(1j * t)
+        iy, iz = np.mod(ky, n), np.mod(kz, n)
+        out[iz, iy, kx] = coef
+        if kx == 0:
+            out[np.mod(-kz, n), np.mod(-ky, n), 0] = np.conj(coef)
+    return out
+
+
+def gravity_wave_spec(n, k=(1, 1, 2), amp_u=0.1, amp_t=0.05, dtype=np.complex128):
+    """One internal-gravity-wave mode k (kx > 0) and its implicit conjugate:
+    uhat(k) = amp_u e, thetahat(k) = amp_t, with e the unit vector along the
+    part of zhat perpendicular to k (the only velocity direction buoyancy
+    forces).  Returns (u [3][n][n][n//2+1], theta [n][n][n//2+1])."""
+    kx, ky, kz = k
+    kv = np.array(k, float)
+    e = np.array([0.0, 0.0, 1.0]) - kv * kv[2] / (kv @ kv)
+    e /= np.linalg.norm(e)
+    u = np.zeros((3, n, n, n // 2 + 1), dtype)
+    t = np.zeros((n, n, n // 2 + 1), dtype)
+    u[:, kz % n, ky % n, kx] = amp_u * e
+    t[kz % n, ky % n, kx] = amp_t
+    return u, t
+
+
 def forcing_shells(n, seed, lo=2, hi=3, energy=1.0, kcut=None, dtype=np.complex128):
     """Constant solenoidal random-phase forcing on shells lo..hi (seed + 1).
     Only the box |k_i| <= hi + 1 can hold those shells, so only it is drawn
