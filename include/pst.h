@@ -2,8 +2,11 @@
  * pst.h -- C ABI of the MI355X-native pseudospectral turbulence hot path.
  *
  * The library evaluates and time-steps the incompressible Navier-Stokes
- * equations (the paper's eq. mom + eq. divv with theta = 0) and, as a second
- * solver, incompressible MHD (eq. uMHD, eq. bMHD) on a periodic n^3 grid of
+ * equations (the paper's eq. mom + eq. divv with theta = 0) and, as further
+ * solvers, incompressible MHD (eq. uMHD, eq. bMHD) and the Boussinesq
+ * equations of a stably stratified fluid (eq. mom, eq. temp, eq. divv: the
+ * velocity and the temperature fluctuation theta, coupled by the buoyancy
+ * terms -N theta zhat and +N w of Brunt-Vaisala frequency N) on a periodic n^3 grid of
  * [0, 2 pi)^3 with the Fourier-Galerkin pseudospectral method of Sec. 2:
  * nonlinear terms are formed in physical space between backward and forward
  * 3D transforms, pressure is applied by projecting onto divergence-free
@@ -31,7 +34,8 @@
  *    (the largest K with 3K < n, alias-free for quadratic products).  The
  *    state only ever holds these modes.
  *  - Time stepping: Lawson integrating factor E = exp(-nu |k|^2 h / 2)
- *    (eta for b) with Heun RK2 or classical RK4.
+ *    (eta for b, kappa = eta for theta) with Heun RK2 or classical RK4; the
+ *    buoyancy coupling is part of the explicit right-hand side.
  *  - "device" pointers are HIP device allocations on the current device;
  *    "host" pointers are ordinary host memory.
  *  - Stream-ordered calls only enqueue work on the plan's stream; synchronous
@@ -56,7 +60,7 @@ typedef enum {
     PST_ERR_UNSUPPORTED = 6    /* option not implemented for this plan */
 } pst_status;
 
-typedef enum { PST_NS = 0, PST_MHD = 1 } pst_solver;
+typedef enum { PST_NS = 0, PST_MHD = 1, PST_BOUSSINESQ = 2 } pst_solver;
 typedef enum { PST_FP32 = 0, PST_FP64 = 1 } pst_precision;
 /* Dealiasing of the nonlinear terms (2/3 rule, K = ceil(n/3) - 1):
  * CUBE keeps max(|kx|, |ky|, |kz|) <= K; SPHERE keeps |k|^2 <= K^2.  The state
@@ -64,7 +68,10 @@ typedef enum { PST_FP32 = 0, PST_FP64 = 1 } pst_precision;
  * no nonlinear term (they evolve by the linear part alone).  Ensembles use the
  * cube. */
 typedef enum { PST_DEALIAS_CUBE = 0, PST_DEALIAS_SPHERE = 1 } pst_dealias;
-typedef enum { PST_FIELD_U = 0, PST_FIELD_B = 1 } pst_field;
+/* U: velocity (3 components); B: magnetic field (MHD, 3 components); THETA:
+ * temperature fluctuation (Boussinesq, 1 component: physical [1][n][n][n],
+ * spectral [1][n][n][n/2+1]). */
+typedef enum { PST_FIELD_U = 0, PST_FIELD_B = 1, PST_FIELD_THETA = 2 } pst_field;
 typedef enum { PST_SPACE_PHYS = 0, PST_SPACE_SPEC = 1 } pst_space;
 typedef enum { PST_MEM_HOST = 0, PST_MEM_DEVICE = 1 } pst_mem;
 
@@ -79,15 +86,16 @@ typedef struct {
     int precision;    /* pst_precision */
     int rk_order;     /* 2 (Heun) or 4 (classical) */
     double nu;        /* kinematic viscosity */
-    double eta;       /* magnetic diffusivity (MHD) */
+    double eta;       /* magnetic diffusivity (MHD) or scalar diffusivity kappa (Boussinesq) */
     double dt;        /* time step h */
     int dealias;      /* pst_dealias */
     unsigned flags;   /* PST_FLAG_* */
+    double nbv;       /* Brunt-Vaisala frequency N (Boussinesq; ignored otherwise) */
 } pst_params;
 
 typedef struct {
     int n, kcut;              /* grid size and dealias cutoff K */
-    int ncomp;                /* state components: 3 (NS) or 6 (MHD) */
+    int ncomp;                /* state components: 3 (NS), 6 (MHD: u, b) or 4 (Boussinesq: u, theta) */
     size_t modes_per_comp;    /* stored modes per component: (K+1)(2K+1)^2 */
     size_t workspace_bytes;   /* device bytes owned by the plan */
     int radices[4];           /* FFT radix schedule of the n-point transforms (0-terminated) */
@@ -133,27 +141,32 @@ pst_status pst_plan_create(const pst_params *p, void *hip_stream, pst_plan **out
 /* Free everything the plan owns (synchronises its stream).  NULL is a no-op. */
 void pst_plan_destroy(pst_plan *plan);
 
-/* Load field u (or b, MHD) from src.  PHYS: real [3][n][n][n]; SPEC: complex
- * [3][n][n][n/2+1].  The data is copied: modes outside the dealiasing cube
+/* Load field u (b for MHD, theta for Boussinesq) from src.  PHYS: real
+ * [nc][n][n][n]; SPEC: complex [nc][n][n][n/2+1], nc = 3 (u, b) or 1 (theta).
+ * INVALID_ARG for a field the solver does not have.  The data is copied: modes outside the dealiasing cube
  * are dropped and the kx = 0 plane is made Hermitian ((X(k) + conj X(-k))/2).
  * mem says where src lives; a HOST copy is synchronous, a DEVICE copy is
  * stream-ordered.  Resets the step counter. */
 pst_status pst_set_state(pst_plan *plan, int field, int space, const void *src, int mem);
 
-/* Write field u (or b) to dst in the layout of pst_set_state (all modes
+/* Write field u (b, theta) to dst in the layout of pst_set_state (all modes
  * outside the cube are zero).  HOST: synchronous; DEVICE: stream-ordered. */
 pst_status pst_get_state(pst_plan *plan, int field, int space, void *dst, int mem);
 
-/* Constant forcing fhat added to the projected NS nonlinear term, spectral
+/* Constant forcing fhat added to the projected nonlinear term of u, spectral
  * layout [3][n][n][n/2+1]; it should be solenoidal (it is dealiased, not
- * projected).  NULL removes the forcing.  NS only.  Synchronous for HOST. */
+ * projected).  NULL removes the forcing.  Navier-Stokes and Boussinesq only.
+ * Synchronous for HOST. */
 pst_status pst_set_forcing(pst_plan *plan, const void *fhat, int mem);
 
 /* Nonlinear right-hand side of the state in state_dev (device, spectral
- * layout; NS: [3] comps of u, MHD: [6] = u then b), written to rhs_dev (same
- * layout):  NS  N = D P F[u x w] + f;  MHD  N_u = D P F[u x w + j x b],
- * N_b = D (i k x F[u x b]).  Viscous terms are excluded.  Stream-ordered.
- * Does not touch the plan's state. */
+ * layout; NS: [3] comps of u, MHD: [6] = u then b, Boussinesq: [4] = u then
+ * theta), written to rhs_dev (same layout):  NS  N = D P F[u x w] + f;  MHD
+ * N_u = D P F[u x w + j x b], N_b = D (i k x F[u x b]);  Boussinesq
+ * N_u = D P (F[u x w] - N thetahat zhat) + f, N_theta = D (-F[u . grad theta]
+ * + N w_z) (eq. mom, eq. temp; u . grad u in rotational form, its gradient
+ * part absorbed by the projection).  Viscous and diffusive terms are
+ * excluded.  Stream-ordered.  Does not touch the plan's state. */
 pst_status pst_rhs(pst_plan *plan, const void *state_dev, void *rhs_dev);
 
 /* Advance the plan's state by nsteps integrating-factor RK steps.
@@ -161,14 +174,15 @@ pst_status pst_rhs(pst_plan *plan, const void *state_dev, void *rhs_dev);
 pst_status pst_step(pst_plan *plan, int nsteps);
 
 /* Energies E = 1/2 <|v|^2> = 1/2 sum_k w |vhat|^2 (w = 1 on kx = 0, else 2)
- * of u and b (out[1] = 0 for NS), accumulated in double.  Synchronous.
- * NONFINITE if either is NaN/Inf. */
+ * of u and of b (MHD) or theta (Boussinesq: 1/2 <theta^2>); out[1] = 0 for
+ * NS.  Accumulated in double.  Synchronous.  NONFINITE if either is NaN/Inf. */
 pst_status pst_energy(pst_plan *plan, double out[2]);
 
-/* Enstrophies Z = 1/2 <|curl v|^2> = 1/2 sum_k w |k|^2 |vhat|^2 of u and b
- * (out[1] = 0 for NS), accumulated in double; with the energy they give the
- * viscous energy loss rate dE/dt = -2 (nu Z_u + eta Z_b) of the unforced
- * equations.  Synchronous.  NONFINITE if either is NaN/Inf. */
+/* Enstrophies Z = 1/2 sum_k w |k|^2 |vhat|^2 of u and of b or theta (out[1]
+ * = 0 for NS; for a solenoidal field Z = 1/2 <|curl v|^2>, for theta
+ * 1/2 <|grad theta|^2>), accumulated in double; with the energies they give
+ * the dissipation rate -2 (nu Z_u + eta Z_2) of the unforced equations.
+ * Synchronous.  NONFINITE if either is NaN/Inf. */
 pst_status pst_enstrophy(pst_plan *plan, double out[2]);
 
 /* Shell spectrum E(s) = 1/2 sum_{floor(|k|+1/2) = s} w |vhat|^2 for

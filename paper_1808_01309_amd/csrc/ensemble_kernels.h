@@ -109,7 +109,7 @@ __device__ __forceinline__ void ens_unit_v(const EnsClass<T>& c, int pass, int s
             zinv_body<T, LC, ENS_NT, 1>(st, A, c.tw, g, lu, tid, sm);
         } break;
         case 1: ypass_body<T, TC, ENS_NT, true>(A, B, c.tw, g, g.sa, g.sb, 6, lu, tid, sm); break;
-        case 2: xpass_body<T, TC, ENS_NT, false>(B, C, c.tw, g, lu, tid, sm); break;
+        case 2: xpass_body<T, TC, ENS_NT, 0>(B, C, c.tw, g, lu, tid, sm); break;
         case 3: ypass_body<T, TC, ENS_NT, false>(C, A, c.tw, g, g.sb, g.sa, 3, lu, tid, sm); break;
         default: {
             RkArgs<T> ra;
@@ -124,7 +124,7 @@ __device__ __forceinline__ void ens_unit_v(const EnsClass<T>& c, int pass, int s
             ra.kf = -1;
             ra.lin_only = 0;
             ra.sph2 = -1;
-            zfwd_body<T, LC, ENS_NT, false>(A, c.tw, g, ra, mode, lu, tid, sm);
+            zfwd_body<T, LC, ENS_NT, 0>(A, c.tw, g, ra, mode, lu, tid, sm);
         } break;
     }
 }

@@ -121,8 +121,10 @@ struct RkArgs {
 
 // ------------------------------------------------------------ zinv + curl
 // One line (kx, jy) per G threads.  NGRP = 1 (u) or 2 (u, b): each group of
-// 3 state components yields 6 fields: v and i k x v.
-template <typename T, class CF, int NT, int NGRP>
+// 3 state components yields 6 fields: v and i k x v.  THETA (Boussinesq): the
+// scalar (state component 3) then yields 4 more fields, i k theta (the
+// gradient) and theta itself.
+template <typename T, class CF, int NT, int NGRP, bool THETA = false>
 __device__ __forceinline__ void zinv_body(const cx<T>* __restrict__ st, cx<T>* __restrict__ A,
                                           const cx<T>* __restrict__ tw, const Geo& geo, int64_t unit, int tid,
                                           cx<T>* sm) {
@@ -179,13 +181,43 @@ __device__ __forceinline__ void zinv_body(const cx<T>* __restrict__ st, cx<T>* _
             }
         }
     }
+    if constexpr (THETA) {
+        const cx<T>* src = st + (int64_t)3 * geo.sc + lin * geo.M;
+        cx<T> th[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = j_of_pos(F::first_pos(g, e), geo);
+            th[e] = (active && j >= 0) ? src[j] : czero<T>();
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<T> w[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const T fk = c == 0 ? fkx : c == 1 ? fky : T(k_of_pos(F::first_pos(g, e), N));
+                w[e] = mul_i(cscale(th[e], fk));
+            }
+            F::run(w, g, lds, tw);
+            if (active) {
+                cx<T>* dst = A + (int64_t)(6 + c) * geo.sa + lin * N;
+#pragma unroll
+                for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = w[e];
+            }
+        }
+        F::run(th, g, lds, tw);
+        if (active) {
+            cx<T>* dst = A + (int64_t)9 * geo.sa + lin * N;
+#pragma unroll
+            for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = th[e];
+        }
+    }
 }
 
-template <typename T, class CF, int NGRP>
+template <typename T, class CF, int NGRP, bool THETA>
 __global__ __launch_bounds__(LINE_BLOCK) void k_zinv(const cx<T>* __restrict__ st, cx<T>* __restrict__ A,
                                                       const cx<T>* __restrict__ tw, Geo geo) {
     __shared__ cx<T> sm[line_lds<T, CF, LINE_BLOCK>()];
-    zinv_body<T, CF, LINE_BLOCK, NGRP>(st, A, tw, geo, blockIdx.x, threadIdx.x, sm);
+    zinv_body<T, CF, LINE_BLOCK, NGRP, THETA>(st, A, tw, geo, blockIdx.x, threadIdx.x, sm);
 }
 
 // ------------------------------------------------------------ y passes
@@ -244,17 +276,19 @@ __global__ __launch_bounds__((CF::G * CF::TL)) void k_ypass(const cx<T>* __restr
 // (v, i k x v) packed as one complex line each (two real transforms for the
 // price of one), cross products in registers, forward x of the products
 // packed two per complex line, split by Hermitian symmetry, kx <= K kept.
-template <typename T, class CF, int NT, bool MHD, bool PPB = false>
+// SYS: 0 Navier-Stokes, 1 MHD, 2 Boussinesq (nbv: Brunt-Vaisala frequency).
+template <typename T, class CF, int NT, int SYS, bool PPB = false>
 __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
                                            const cx<T>* __restrict__ tw, const Geo& geo, int64_t unit, int tid,
-                                           cx<T>* sm) {
+                                           cx<T>* sm, T nbv = T(0)) {
+    constexpr bool MHD = SYS == 1, BQ = SYS == 2;
     constexpr int N = CF::N, G = CF::G, TL = CF::TL, TLP = TL + 1, TT = G * TL, SG = NT / TT;
     using FI = Fft<T, typename CF::P, G, true, false>;
     using FF = Fft<T, typename CF::P, G, false, true>;
     constexpr int E = FI::E, NTZ = ztiles<N, TL>();
-    constexpr int NP = MHD ? 6 : 3;   // backward pairs
-    constexpr int NO = MHD ? 3 : 2;   // forward packed lines
-    constexpr int NOUT = MHD ? 6 : 3; // output fields
+    constexpr int NP = MHD ? 6 : BQ ? 5 : 3;   // backward pairs
+    constexpr int NO = MHD ? 3 : 2;            // forward packed lines
+    constexpr int NOUT = MHD ? 6 : BQ ? 4 : 3; // output fields
     const int s = tid / TT, r = tid % TT;
     const int t = r % TL, g = r / TL;
     const int64_t tile = unit * SG + s;
@@ -281,7 +315,9 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     for (int pi = 0; pi < NP; ++pi) {
         // this tile's LDS (2 (K+1) TLP <= N TLP)
         cx<T>* const stage = sm + ((PPB && (ex & 1)) ? TSZ : 0) + s * N * TLP;
-        const int fu = (pi / 3) * 6 + pi % 3, fw = fu + 3;
+        // pairs (v_c, (i k x v)_c); Boussinesq adds (theta_x, theta_y), (theta_z, theta)
+        const int fu = (BQ && pi >= 3) ? 6 + 2 * (pi - 3) : (pi / 3) * 6 + pi % 3;
+        const int fw = (BQ && pi >= 3) ? fu + 1 : fu + 3;
         for (int kx = g; kx <= K; kx += G) {
             stage[kx * TLP + t] = zin ? Bf[fu * geo.sb + kx * nn + off] : czero<T>();
             stage[(K + 1 + kx) * TLP + t] = zin ? Bf[fw * geo.sb + kx * nn + off] : czero<T>();
@@ -330,6 +366,12 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
             v[0][e] = {nx, ny};
             v[1][e] = {nz, mx};
             v[2][e] = {my, mz};
+        } else if constexpr (BQ) {
+            // buoyancy -N theta zhat joins the momentum products; the scalar's
+            // term is -u . grad theta + N u_z
+            const T gx = v[3][e].x, gy = v[3][e].y, gz = v[4][e].x, th = v[4][e].y;
+            v[0][e] = {nx, ny};
+            v[1][e] = {nz - nbv * th, nbv * uz - (ux * gx + uy * gy + uz * gz)};
         } else {
             v[0][e] = {nx, ny};
             v[1][e] = {nz, T(0)};
@@ -378,23 +420,23 @@ template <typename T, class CF, bool MHD> constexpr int xpass_per() {
     return (sizeof(T) == 8 && xpass_pp<T, CF, MHD>()) ? 32 : 1;
 }
 
-template <typename T, class CF, bool MHD>
+template <typename T, class CF, int SYS>
 __global__ __launch_bounds__((CF::G * CF::TL)) void k_xpass(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
-                                                          const cx<T>* __restrict__ tw, Geo geo) {
-    constexpr bool PPB = xpass_pp<T, CF, MHD>();
-    constexpr int PER = xpass_per<T, CF, MHD>();
+                                                          const cx<T>* __restrict__ tw, Geo geo, T nbv) {
+    constexpr bool PPB = xpass_pp<T, CF, SYS == 1>();
+    constexpr int PER = xpass_per<T, CF, SYS == 1>();
     __shared__ cx<T> sm[(PPB ? 2 : 1) * tile_lds<T, CF, CF::G * CF::TL>()];
     // each XCD takes a contiguous range of tiles (measured faster, most for the
     // narrow MHD tiles at n = 1024 whose rows share cache lines)
     if constexpr (PER == 1) {
-        xpass_body<T, CF, CF::G * CF::TL, MHD, PPB>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm);
+        xpass_body<T, CF, CF::G * CF::TL, SYS, PPB>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm, nbv);
     } else {
         const int64_t ntl = (int64_t)CF::N * ztiles<CF::N, CF::TL>();
         const int64_t u0 = xcd_unit() * PER;
         const int64_t u1 = u0 + PER < ntl ? u0 + PER : ntl;
         for (int64_t u = u0; u < u1; ++u) {
             if (u > u0) __syncthreads();   // the previous tile's last LDS reads
-            xpass_body<T, CF, CF::G * CF::TL, MHD, PPB>(Bf, Cf, tw, geo, u, threadIdx.x, sm);
+            xpass_body<T, CF, CF::G * CF::TL, SYS, PPB>(Bf, Cf, tw, geo, u, threadIdx.x, sm, nbv);
         }
     }
 }
@@ -443,7 +485,7 @@ __device__ __forceinline__ void rk_apply(int mode, cx<T>* __restrict__ U, cx<T>*
     }
 }
 
-template <typename T, class CF, int NT, bool MHD>
+template <typename T, class CF, int NT, int SYS>
 __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw, const Geo& geo,
                                            const RkArgs<T>& ra, cx<T>* __restrict__ U, cx<T>* __restrict__ V,
                                            cx<T>* __restrict__ Acc, cx<T>* __restrict__ R, int mode, int64_t unit,
@@ -451,7 +493,8 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
     constexpr int N = CF::N, G = CF::G;
     using F = Fft<T, typename CF::P, G, false>;
     constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
-    constexpr int NF = MHD ? 6 : 3;
+    constexpr bool MHD = SYS == 1, BQ = SYS == 2;
+    constexpr int NF = MHD ? 6 : BQ ? 4 : 3;
     const int l = tid / G, g = tid % G;
     const int64_t line = unit * LPB + l;
     const bool active = line < (int64_t)geo.nxk * geo.M;
@@ -520,20 +563,27 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
 #pragma unroll
             for (int c = 0; c < 3; ++c) rk_apply(mode, U, V, Acc, R, ra.h, (3 + c) * geo.sc + idx, Eb, E2b, b[c]);
         }
+        if constexpr (BQ) {
+            // scalar: D (-F[u . grad theta] + N w_z), its own integrating factor
+            cx<T> q = cscale(v[3][e], scale);
+            if (ra.lin_only || cut) q = czero<T>();
+            rk_apply(mode, U, V, Acc, R, ra.h, 3 * geo.sc + idx, ra.E[1][k2], ra.E2[1][k2], q);
+        }
     }
 }
 
-template <typename T, class CF, int NT, bool MHD>
+// SYS: 0 Navier-Stokes, 1 MHD, 2 Boussinesq.
+template <typename T, class CF, int NT, int SYS>
 __device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw, const Geo& geo,
                                           const RkArgs<T>& ra, int mode, int64_t unit, int tid, cx<T>* sm) {
-    zfwd_lines<T, CF, NT, MHD>(D, tw, geo, ra, ra.U, ra.V, ra.Acc, ra.R, mode, unit, tid, sm);
+    zfwd_lines<T, CF, NT, SYS>(D, tw, geo, ra, ra.U, ra.V, ra.Acc, ra.R, mode, unit, tid, sm);
 }
 
-template <typename T, class CF, bool MHD>
+template <typename T, class CF, int SYS>
 __global__ __launch_bounds__(LINE_BLOCK) void k_zfwd(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw,
                                                       Geo geo, RkArgs<T> ra, int mode) {
     __shared__ cx<T> sm[line_lds<T, CF, LINE_BLOCK>()];
-    zfwd_body<T, CF, LINE_BLOCK, MHD>(D, tw, geo, ra, mode, blockIdx.x, threadIdx.x, sm);
+    zfwd_body<T, CF, LINE_BLOCK, SYS>(D, tw, geo, ra, mode, blockIdx.x, threadIdx.x, sm);
 }
 
 // ------------------------------------------------------------ standalone FFTs
@@ -782,11 +832,14 @@ struct Impl {
         KTimer tm(P, PST_K_ZINV);
         const Geo& g = P->geo;
         const unsigned nb = (unsigned)line_units<LC, LINE_BLOCK>(g);
-        if (P->ncomp == 6)
-            hipLaunchKernelGGL((k_zinv<T, LC, 2>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
+        if (P->p.solver == PST_MHD)
+            hipLaunchKernelGGL((k_zinv<T, LC, 2, false>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
+                               (cx<T>*)P->A, (const cx<T>*)P->tw, g);
+        else if (P->p.solver == PST_BOUSSINESQ)
+            hipLaunchKernelGGL((k_zinv<T, LC, 1, true>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
                                (cx<T>*)P->A, (const cx<T>*)P->tw, g);
         else
-            hipLaunchKernelGGL((k_zinv<T, LC, 1>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
+            hipLaunchKernelGGL((k_zinv<T, LC, 1, false>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
                                (cx<T>*)P->A, (const cx<T>*)P->tw, g);
     }
     static void yinv(pst_plan* P) {
@@ -799,17 +852,24 @@ struct Impl {
     static void xpass(pst_plan* P) {
         KTimer tm(P, PST_K_XPASS);
         const Geo& g = P->geo;
-        if (P->ncomp == 6) {
+        if (P->p.solver == PST_MHD) {
             using XC = XCfg<T, N, true>;
-            hipLaunchKernelGGL((k_xpass<T, XC, true>), dim3((unsigned)xtile_units<XC, XC::G * XC::TL>()),
+            hipLaunchKernelGGL((k_xpass<T, XC, 1>), dim3((unsigned)xtile_units<XC, XC::G * XC::TL>()),
                                dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
-                               (const cx<T>*)P->tw, g);
+                               (const cx<T>*)P->tw, g, T(0));
+        } else if (P->p.solver == PST_BOUSSINESQ) {
+            // five backward pairs: the MHD tile (half the lines) keeps them in registers
+            using XC = XCfg<T, N, true>;
+            constexpr int per = xpass_per<T, XC, false>();
+            hipLaunchKernelGGL((k_xpass<T, XC, 2>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(), per)),
+                               dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
+                               (const cx<T>*)P->tw, g, (T)P->p.nbv);
         } else {
             using XC = XCfg<T, N, false>;
             constexpr int per = xpass_per<T, XC, false>();
-            hipLaunchKernelGGL((k_xpass<T, XC, false>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(), per)),
+            hipLaunchKernelGGL((k_xpass<T, XC, 0>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(), per)),
                                dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
-                               (const cx<T>*)P->tw, g);
+                               (const cx<T>*)P->tw, g, T(0));
         }
     }
     static void yfwd(pst_plan* P) {
@@ -837,11 +897,14 @@ struct Impl {
         ra.lin_only = (P->p.flags & PST_FLAG_LINEAR_ONLY) ? 1 : 0;
         ra.sph2 = P->p.dealias == PST_DEALIAS_SPHERE ? g.K * g.K : -1;
         const unsigned nb = (unsigned)line_units<LC, LINE_BLOCK>(g);
-        if (P->ncomp == 6)
-            hipLaunchKernelGGL((k_zfwd<T, LC, true>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+        if (P->p.solver == PST_MHD)
+            hipLaunchKernelGGL((k_zfwd<T, LC, 1>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+                               (const cx<T>*)P->tw, g, ra, mode);
+        else if (P->p.solver == PST_BOUSSINESQ)
+            hipLaunchKernelGGL((k_zfwd<T, LC, 2>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
                                (const cx<T>*)P->tw, g, ra, mode);
         else
-            hipLaunchKernelGGL((k_zfwd<T, LC, false>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+            hipLaunchKernelGGL((k_zfwd<T, LC, 0>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
                                (const cx<T>*)P->tw, g, ra, mode);
     }
     static void fft_r2c(pst_plan* P, const void* in, void* out, int nf) {

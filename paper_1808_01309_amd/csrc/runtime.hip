@@ -166,11 +166,11 @@ __global__ void k_scatter(const cx<T>* __restrict__ st, cx<T>* __restrict__ abi,
 }
 
 // Energy partials: block b sums w |v|^2 over its grid-stride share of the
-// modes of components [c0, c0 + 3) in a fixed order -> partial[b] (double).
+// modes of components [c0, c0 + nc) in a fixed order -> partial[b] (double).
 constexpr int RED_BLOCKS = 1024, RED_THREADS = 256;
 
 template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void k_energy_part(const cx<T>* __restrict__ st, Geo g, int c0,
+__global__ __launch_bounds__(RED_THREADS) void k_energy_part(const cx<T>* __restrict__ st, Geo g, int c0, int nc,
                                                              double* __restrict__ part, int k2w) {
     __shared__ double sh[RED_THREADS];
     double acc = 0.0;
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_energy_part(const cx<T>* __rest
             w *= (double)(kx * kx + ky * ky + kz * kz);
         }
         double s = 0.0;
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < nc; ++c) {
             const cx<T> v = st[(int64_t)(c0 + c) * per + i];
             s += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
         }
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_sum_final(const double* __restr
 constexpr int MAX_SHELLS = 2048;
 
 template <typename T>
-__global__ __launch_bounds__(RED_THREADS) void k_spectrum(const cx<T>* __restrict__ st, Geo g, int c0,
+__global__ __launch_bounds__(RED_THREADS) void k_spectrum(const cx<T>* __restrict__ st, Geo g, int c0, int nc,
                                                           double* __restrict__ bins, int nshells) {
     __shared__ double sh[MAX_SHELLS];
     for (int i = threadIdx.x; i < nshells; i += RED_THREADS) sh[i] = 0.0;
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_spectrum(const cx<T>* __restric
         const int s = (int)floor(sqrt((double)k2) + 0.5);
         if (s >= nshells) continue;
         double a = 0.0;
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < nc; ++c) {
             const cx<T> v = st[(int64_t)(c0 + c) * per + i];
             a += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
         }
@@ -329,14 +329,17 @@ extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst
     if (!out) return fail(nullptr, PST_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!p) return fail(nullptr, PST_ERR_INVALID_ARG, "params is NULL");
-    if (p->solver != PST_NS && p->solver != PST_MHD) return fail(nullptr, PST_ERR_INVALID_ARG, "solver %d", p->solver);
+    if (p->solver != PST_NS && p->solver != PST_MHD && p->solver != PST_BOUSSINESQ)
+        return fail(nullptr, PST_ERR_INVALID_ARG, "solver %d", p->solver);
     if (p->precision != PST_FP32 && p->precision != PST_FP64)
         return fail(nullptr, PST_ERR_INVALID_ARG, "precision %d", p->precision);
     if (p->rk_order != 2 && p->rk_order != 4) return fail(nullptr, PST_ERR_INVALID_ARG, "rk_order %d", p->rk_order);
     if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(nullptr, PST_ERR_INVALID_ARG, "dt must be > 0");
     if (!(p->nu >= 0.0) || !isfinite(p->nu)) return fail(nullptr, PST_ERR_INVALID_ARG, "nu must be >= 0");
-    if (p->solver == PST_MHD && (!(p->eta >= 0.0) || !isfinite(p->eta)))
+    if (p->solver != PST_NS && (!(p->eta >= 0.0) || !isfinite(p->eta)))
         return fail(nullptr, PST_ERR_INVALID_ARG, "eta must be >= 0");
+    if (p->solver == PST_BOUSSINESQ && !isfinite(p->nbv))
+        return fail(nullptr, PST_ERR_INVALID_ARG, "nbv must be finite");
     if (p->dealias != PST_DEALIAS_CUBE && p->dealias != PST_DEALIAS_SPHERE)
         return fail(nullptr, PST_ERR_UNSUPPORTED, "dealias %d", p->dealias);
     if (p->flags & ~(unsigned)(PST_FLAG_LINEAR_ONLY | PST_FLAG_TIMERS))
@@ -359,10 +362,12 @@ extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst
     P->geo.sc = (int64_t)(K + 1) * M * M;
     P->geo.sa = (int64_t)(K + 1) * M * n;
     P->geo.sb = (int64_t)(K + 1) * n * n;
-    const bool mhd = p->solver == PST_MHD;
-    P->ncomp = mhd ? 6 : 3;
-    P->nfin = mhd ? 12 : 6;
-    P->nfout = mhd ? 6 : 3;
+    const bool mhd = p->solver == PST_MHD, bq = p->solver == PST_BOUSSINESQ;
+    // state components; fields of the backward passes (v, i k x v per vector
+    // field; grad theta and theta) and of the forward passes
+    P->ncomp = mhd ? 6 : bq ? 4 : 3;
+    P->nfin = mhd ? 12 : bq ? 10 : 6;
+    P->nfout = mhd ? 6 : bq ? 4 : 3;
     P->kf = -1;
     const size_t es = P->esz, tsz = p->precision == PST_FP64 ? 8 : 4;
     pst_status s = PST_OK;
@@ -422,14 +427,26 @@ extern "C" pst_status pst_query(const pst_plan* P, pst_info* info) {
 
 // --------------------------------------------------------------- state I/O
 static bool valid_field(const pst_plan* P, int field) {
-    return field == PST_FIELD_U || (field == PST_FIELD_B && P->ncomp == 6);
+    return field == PST_FIELD_U || (field == PST_FIELD_B && P->p.solver == PST_MHD) ||
+           (field == PST_FIELD_THETA && P->p.solver == PST_BOUSSINESQ);
+}
+// first state component and component count of a field
+static int field_c0(int field) { return field == PST_FIELD_U ? 0 : 3; }
+static int field_nc(int field) { return field == PST_FIELD_THETA ? 1 : 3; }
+// the fields of the state, in component order
+static int state_fields(const pst_plan* P, int* f) {
+    f[0] = PST_FIELD_U;
+    if (P->p.solver == PST_MHD) f[1] = PST_FIELD_B;
+    else if (P->p.solver == PST_BOUSSINESQ) f[1] = PST_FIELD_THETA;
+    else return 1;
+    return 2;
 }
 
 template <typename T>
-static void launch_gather(pst_plan* P, const void* abi, void* st) {
+static void launch_gather(pst_plan* P, const void* abi, void* st, int nc) {
     KTimer tm(P, PST_K_OTHER);
-    hipLaunchKernelGGL((k_gather<T>), dim3(grid_for(3 * P->geo.sc)), dim3(256), 0, P->stream, (const cx<T>*)abi,
-                       (cx<T>*)st, P->geo, 3);
+    hipLaunchKernelGGL((k_gather<T>), dim3(grid_for(nc * P->geo.sc)), dim3(256), 0, P->stream, (const cx<T>*)abi,
+                       (cx<T>*)st, P->geo, nc);
 }
 template <typename T>
 static void launch_scatter(pst_plan* P, const void* st, void* abi, int ncomp) {
@@ -439,9 +456,9 @@ static void launch_scatter(pst_plan* P, const void* st, void* abi, int ncomp) {
                        (cx<T>*)abi, P->geo, ncomp);
 }
 
-static void gather(pst_plan* P, const void* abi, void* st) {
-    if (P->p.precision == PST_FP64) launch_gather<double>(P, abi, st);
-    else launch_gather<float>(P, abi, st);
+static void gather(pst_plan* P, const void* abi, void* st, int nc) {
+    if (P->p.precision == PST_FP64) launch_gather<double>(P, abi, st, nc);
+    else launch_gather<float>(P, abi, st, nc);
 }
 static void scatter(pst_plan* P, const void* st, void* abi, int ncomp) {
     if (P->p.precision == PST_FP64) launch_scatter<double>(P, st, abi, ncomp);
@@ -455,9 +472,10 @@ extern "C" pst_status pst_set_state(pst_plan* P, int field, int space, const voi
     if (space != PST_SPACE_PHYS && space != PST_SPACE_SPEC) return fail(P, PST_ERR_INVALID_ARG, "space %d", space);
     if (mem != PST_MEM_HOST && mem != PST_MEM_DEVICE) return fail(P, PST_ERR_INVALID_ARG, "mem %d", mem);
     const size_t n = P->p.n;
-    const size_t spec = abi_spec_bytes(P, 3);
-    const size_t phys = 3 * n * n * n * (P->esz / 2);
-    // layout of the scratch: [spectral (3 comps)] [physical staging if needed]
+    const int nc = field_nc(field);
+    const size_t spec = abi_spec_bytes(P, nc);
+    const size_t phys = nc * n * n * n * (P->esz / 2);
+    // layout of the scratch: [spectral (nc comps)] [physical staging if needed]
     const size_t need = spec + ((space == PST_SPACE_PHYS && mem == PST_MEM_HOST) ? phys : 0);
     pst_status s = ensure_abi(P, need);
     if (s) return s;
@@ -474,11 +492,11 @@ extern "C" pst_status pst_set_state(pst_plan* P, int field, int space, const voi
             HIPCHK(P, hipMemcpyAsync(spec_buf + spec, src, phys, hipMemcpyHostToDevice, P->stream));
             phys_dev = spec_buf + spec;
         }
-        P->L->fft_r2c(P, phys_dev, spec_buf, 3);
+        P->L->fft_r2c(P, phys_dev, spec_buf, nc);
         if ((s = check_launch(P, "fft_r2c"))) return s;
     }
-    char* st = (char*)P->U + (size_t)field * 3 * P->geo.sc * P->esz;
-    gather(P, spec_buf, st);
+    char* st = (char*)P->U + (size_t)field_c0(field) * P->geo.sc * P->esz;
+    gather(P, spec_buf, st, nc);
     if ((s = check_launch(P, "gather"))) return s;
     if (mem == PST_MEM_HOST) HIPCHK(P, hipStreamSynchronize(P->stream));
     P->steps = 0;
@@ -492,26 +510,27 @@ extern "C" pst_status pst_get_state(pst_plan* P, int field, int space, void* dst
     if (space != PST_SPACE_PHYS && space != PST_SPACE_SPEC) return fail(P, PST_ERR_INVALID_ARG, "space %d", space);
     if (mem != PST_MEM_HOST && mem != PST_MEM_DEVICE) return fail(P, PST_ERR_INVALID_ARG, "mem %d", mem);
     const size_t n = P->p.n;
-    const size_t spec = abi_spec_bytes(P, 3);
-    const size_t phys = 3 * n * n * n * (P->esz / 2);
+    const int nc = field_nc(field);
+    const size_t spec = abi_spec_bytes(P, nc);
+    const size_t phys = nc * n * n * n * (P->esz / 2);
     // scratch: [spectral] [c2r workspace (spectral)] [physical staging]
     const size_t need = space == PST_SPACE_SPEC ? spec : 2 * spec + (mem == PST_MEM_HOST ? phys : 0);
     pst_status s = ensure_abi(P, need);
     if (s) return s;
     char* spec_buf = (char*)P->abi;
-    const char* st = (const char*)P->U + (size_t)field * 3 * P->geo.sc * P->esz;
+    const char* st = (const char*)P->U + (size_t)field_c0(field) * P->geo.sc * P->esz;
     if (space == PST_SPACE_SPEC) {
         void* target = mem == PST_MEM_DEVICE ? dst : (void*)spec_buf;
-        scatter(P, st, target, 3);
+        scatter(P, st, target, nc);
         if ((s = check_launch(P, "scatter"))) return s;
         if (mem == PST_MEM_HOST) {
             HIPCHK(P, hipMemcpyAsync(dst, spec_buf, spec, hipMemcpyDeviceToHost, P->stream));
             HIPCHK(P, hipStreamSynchronize(P->stream));
         }
     } else {
-        scatter(P, st, spec_buf, 3);
+        scatter(P, st, spec_buf, nc);
         void* target = mem == PST_MEM_DEVICE ? dst : (void*)(spec_buf + 2 * spec);
-        P->L->fft_c2r(P, spec_buf, target, 3, spec_buf + spec);
+        P->L->fft_c2r(P, spec_buf, target, nc, spec_buf + spec);
         if ((s = check_launch(P, "fft_c2r"))) return s;
         if (mem == PST_MEM_HOST) {
             HIPCHK(P, hipMemcpyAsync(dst, target, phys, hipMemcpyDeviceToHost, P->stream));
@@ -577,7 +596,8 @@ static pst_status set_forcing_t(pst_plan* P, const cx<T>* h /*host ABI layout*/)
 
 extern "C" pst_status pst_set_forcing(pst_plan* P, const void* fhat, int mem) {
     if (!P) return PST_ERR_INVALID_ARG;
-    if (P->ncomp != 3) return fail(P, PST_ERR_INVALID_ARG, "forcing is defined for the Navier-Stokes solver only");
+    if (P->p.solver == PST_MHD)
+        return fail(P, PST_ERR_INVALID_ARG, "forcing is defined for the Navier-Stokes and Boussinesq solvers only");
     if (mem != PST_MEM_HOST && mem != PST_MEM_DEVICE) return fail(P, PST_ERR_INVALID_ARG, "mem %d", mem);
     const size_t bytes = abi_spec_bytes(P, 3);
     std::vector<char> host;
@@ -626,9 +646,12 @@ extern "C" pst_status pst_rhs(pst_plan* P, const void* state_dev, void* rhs_dev)
     char* cst = (char*)P->abi;          // compact copy of the input state
     char* crhs = cst + cbytes;          // compact rhs
     (void)spec;
-    for (int grp = 0; grp < P->ncomp / 3; ++grp) {
-        const char* src = (const char*)state_dev + (size_t)grp * abi_spec_bytes(P, 3);
-        gather(P, src, cst + (size_t)grp * 3 * P->geo.sc * P->esz);
+    int fl[2];
+    const int nfl = state_fields(P, fl);
+    for (int i = 0; i < nfl; ++i) {
+        const int c0 = field_c0(fl[i]);
+        const char* src = (const char*)state_dev + (size_t)c0 * abi_spec_bytes(P, 1);
+        gather(P, src, cst + (size_t)c0 * P->geo.sc * P->esz, field_nc(fl[i]));
     }
     if ((s = check_launch(P, "gather"))) return s;
     if ((s = run_rhs_passes(P, cst, Z_RHS, crhs))) return s;
@@ -655,10 +678,10 @@ extern "C" pst_status pst_step(pst_plan* P, int nsteps) {
 
 // --------------------------------------------------------------- diagnostics
 template <typename T>
-static void launch_energy(pst_plan* P, int c0, double* out, int k2w) {
+static void launch_energy(pst_plan* P, int c0, int nc, double* out, int k2w) {
     KTimer tm(P, PST_K_OTHER);
     hipLaunchKernelGGL((k_energy_part<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, P->stream, (const cx<T>*)P->U,
-                       P->geo, c0, P->red, k2w);
+                       P->geo, c0, nc, P->red, k2w);
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(RED_THREADS), 0, P->stream, P->red, RED_BLOCKS, out, 0.5);
 }
 
@@ -666,17 +689,19 @@ static void launch_energy(pst_plan* P, int c0, double* out, int k2w) {
 static pst_status quadratic_diag(pst_plan* P, double out[2], int k2w, const char* what) {
     if (!P || !out) return P ? fail(P, PST_ERR_INVALID_ARG, "out is NULL") : PST_ERR_INVALID_ARG;
     double* res = P->red + RED_BLOCKS + MAX_SHELLS;
-    for (int grp = 0; grp < P->ncomp / 3; ++grp) {
-        if (P->p.precision == PST_FP64) launch_energy<double>(P, grp * 3, res + grp, k2w);
-        else launch_energy<float>(P, grp * 3, res + grp, k2w);
+    int fl[2];
+    const int nfl = state_fields(P, fl);
+    for (int i = 0; i < nfl; ++i) {
+        if (P->p.precision == PST_FP64) launch_energy<double>(P, field_c0(fl[i]), field_nc(fl[i]), res + i, k2w);
+        else launch_energy<float>(P, field_c0(fl[i]), field_nc(fl[i]), res + i, k2w);
     }
     pst_status s = check_launch(P, what);
     if (s) return s;
     double h[2] = {0.0, 0.0};
-    HIPCHK(P, hipMemcpyAsync(h, res, sizeof(double) * (P->ncomp / 3), hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(P, hipMemcpyAsync(h, res, sizeof(double) * nfl, hipMemcpyDeviceToHost, P->stream));
     HIPCHK(P, hipStreamSynchronize(P->stream));
     out[0] = h[0];
-    out[1] = P->ncomp == 6 ? h[1] : 0.0;
+    out[1] = nfl == 2 ? h[1] : 0.0;
     if (!isfinite(out[0]) || !isfinite(out[1])) return fail(P, PST_ERR_NONFINITE, "%s is not finite", what);
     return PST_OK;
 }
@@ -699,10 +724,10 @@ extern "C" pst_status pst_spectrum(pst_plan* P, int field, double* Ek, int nshel
         KTimer tm(P, PST_K_OTHER);
         if (P->p.precision == PST_FP64)
             hipLaunchKernelGGL((k_spectrum<double>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, P->stream,
-                               (const cx<double>*)P->U, P->geo, field * 3, bins, nshells);
+                               (const cx<double>*)P->U, P->geo, field_c0(field), field_nc(field), bins, nshells);
         else
             hipLaunchKernelGGL((k_spectrum<float>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, P->stream,
-                               (const cx<float>*)P->U, P->geo, field * 3, bins, nshells);
+                               (const cx<float>*)P->U, P->geo, field_c0(field), field_nc(field), bins, nshells);
     }
     pst_status s = check_launch(P, "spectrum");
     if (s) return s;

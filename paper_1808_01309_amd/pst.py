@@ -28,9 +28,11 @@ lib = ctypes.CDLL(LIB_PATH)
 # ------------------------------------------------------------------ ABI types
 PST_OK, PST_ERR_INVALID_ARG, PST_ERR_UNSUPPORTED_N, PST_ERR_OOM, PST_ERR_HIP, PST_ERR_NONFINITE, \
     PST_ERR_UNSUPPORTED = range(7)
-PST_NS, PST_MHD = 0, 1
+PST_NS, PST_MHD, PST_BOUSSINESQ = 0, 1, 2
 PST_FP32, PST_FP64 = 0, 1
-PST_FIELD_U, PST_FIELD_B = 0, 1
+PST_FIELD_U, PST_FIELD_B, PST_FIELD_THETA = 0, 1, 2
+_FIELDS = {"u": PST_FIELD_U, "b": PST_FIELD_B, "theta": PST_FIELD_THETA}
+_SOLVERS = {"ns": PST_NS, "mhd": PST_MHD, "boussinesq": PST_BOUSSINESQ}
 PST_SPACE_PHYS, PST_SPACE_SPEC = 0, 1
 PST_MEM_HOST, PST_MEM_DEVICE = 0, 1
 PST_FLAG_LINEAR_ONLY, PST_FLAG_TIMERS = 1, 2
@@ -40,7 +42,8 @@ KERNEL_KINDS = ["zinv", "yinv", "xpass", "yfwd", "zfwd", "fftx", "ffty", "fftz",
 class pst_params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("solver", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rk_order", ctypes.c_int), ("nu", ctypes.c_double), ("eta", ctypes.c_double),
-                ("dt", ctypes.c_double), ("dealias", ctypes.c_int), ("flags", ctypes.c_uint)]
+                ("dt", ctypes.c_double), ("dealias", ctypes.c_int), ("flags", ctypes.c_uint),
+                ("nbv", ctypes.c_double)]
 
 
 class pst_info(ctypes.Structure):
@@ -152,17 +155,22 @@ class Plan:
     """One solver plan (pst_plan_create ... pst_plan_destroy)."""
 
     def __init__(self, n, solver="ns", precision="fp32", rk_order=4, nu=0.0, eta=None, dt=1e-3,
-                 linear_only=False, timers=False, stream=None, dealias="cube"):
-        p = pst_params(n=n, solver=PST_MHD if solver == "mhd" else PST_NS,
+                 linear_only=False, timers=False, stream=None, dealias="cube", kappa=None, nbv=0.0):
+        """solver: "ns", "mhd" (eta: magnetic diffusivity) or "boussinesq"
+        (kappa: scalar diffusivity, default nu; nbv: Brunt-Vaisala frequency)."""
+        second = kappa if solver == "boussinesq" else eta
+        p = pst_params(n=n, solver=_SOLVERS[solver],
                        precision=PST_FP64 if precision == "fp64" else PST_FP32, rk_order=rk_order,
-                       nu=nu, eta=nu if eta is None else eta, dt=dt,
+                       nu=nu, eta=nu if second is None else second, dt=dt,
                        dealias={"cube": 0, "sphere": 1}[dealias],
-                       flags=(PST_FLAG_LINEAR_ONLY if linear_only else 0) | (PST_FLAG_TIMERS if timers else 0))
+                       flags=(PST_FLAG_LINEAR_ONLY if linear_only else 0) | (PST_FLAG_TIMERS if timers else 0),
+                       nbv=nbv)
         self.params = p
         self.n = n
         self.fp64 = precision == "fp64"
         self.mhd = solver == "mhd"
-        self.ncomp = 6 if self.mhd else 3
+        self.solver = solver
+        self.ncomp = {"ns": 3, "mhd": 6, "boussinesq": 4}[solver]
         self.real_np = np.float64 if self.fp64 else np.float32
         self.cplx_np = np.complex128 if self.fp64 else np.complex64
         h = _P()
@@ -200,8 +208,9 @@ class Plan:
     # --------------------------------------------------------------- ABI calls
     def set_state(self, data, field="u", space=None):
         """data: numpy (host) or torch (device) array, spectral complex
-        [3][n][n][n/2+1] or physical real [3][n][n][n]."""
-        f = PST_FIELD_B if field == "b" else PST_FIELD_U
+        [nc][n][n][n/2+1] or physical real [nc][n][n][n] (nc = 3 for u and b,
+        1 for theta, which may also be given without the leading axis)."""
+        f = _FIELDS[field]
         if space is None:
             space = "spec" if np.iscomplexobj(np.empty(0, dtype=_np_dtype(data))) else "phys"
         if isinstance(data, np.ndarray):
@@ -211,10 +220,11 @@ class Plan:
                                       ptr, mem))
 
     def get_state(self, field="u", space="spec", out=None):
-        f = PST_FIELD_B if field == "b" else PST_FIELD_U
+        f = _FIELDS[field]
         sp = PST_SPACE_SPEC if space == "spec" else PST_SPACE_PHYS
+        nc = 1 if field == "theta" else 3
         if out is None:
-            out = np.empty(self.spec_shape() if space == "spec" else self.phys_shape(),
+            out = np.empty(self.spec_shape(nc) if space == "spec" else self.phys_shape(nc),
                            self.cplx_np if space == "spec" else self.real_np)
         ptr, mem = _ptr(out)
         self._check(lib.pst_get_state(self._h, f, sp, ptr, mem))
@@ -251,8 +261,7 @@ class Plan:
         if nshells is None:
             nshells = int(np.floor(np.sqrt(3.0) * kcut_23(self.n) + 0.5)) + 1
         out = np.zeros(nshells, np.float64)
-        self._check(lib.pst_spectrum(self._h, PST_FIELD_B if field == "b" else PST_FIELD_U,
-                                     out.ctypes.data_as(_P), nshells))
+        self._check(lib.pst_spectrum(self._h, _FIELDS[field], out.ctypes.data_as(_P), nshells))
         return out
 
     def fft_r2c(self, x, out, nfields):
