@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-fno", action="store_true")
     ap.add_argument("--no-mhd", action="store_true")
+    ap.add_argument("--no-bq", action="store_true")
     ap.add_argument("--surrogate", action="store_true",
                     help="run the whole surrogate pipeline (data, ~70 s of training, evaluation, timed "
                          "hybrid rollout) instead of reporting its committed summary")
@@ -59,20 +60,22 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_bytes(n, esz, rk, mhd=False):
+def kernel_bytes(n, esz, rk, mhd=False, bq=False):
     """Algorithmic HBM bytes per launch of each solver kernel: every array
-    element a pass must read or write, once (MHD: twice the fields)."""
+    element a pass must read or write, once.  State components / backward
+    fields / forward fields: 3 / 6 / 3 (Navier-Stokes), 6 / 12 / 6 (MHD),
+    4 / 10 / 4 (Boussinesq: u, theta; v, i k x v, grad theta, theta)."""
     K = -(-n // 3) - 1
     M, nxk = 2 * K + 1, K + 1
     sc, sa, sb = nxk * M * M, nxk * M * n, nxk * n * n
     rk_arrays = 13.0 / 4.0 if rk == 4 else 5.0 / 2.0  # state-sized arrays touched per stage update
-    g = 2 if mhd else 1
+    ns, nb, nf = (6, 12, 6) if mhd else (4, 10, 4) if bq else (3, 6, 3)
     return {
-        "zinv": g * (3 * sc + 6 * sa) * esz,
-        "yinv": g * (6 * sa + 6 * sb) * esz,
-        "xpass": g * (6 * sb + 3 * sb) * esz,
-        "yfwd": g * (3 * sb + 3 * sa) * esz,
-        "zfwd": g * (3 * sa + rk_arrays * 3 * sc) * esz,
+        "zinv": (ns * sc + nb * sa) * esz,
+        "yinv": (nb * sa + nb * sb) * esz,
+        "xpass": (nb * sb + nf * sb) * esz,
+        "yfwd": (nf * sb + nf * sa) * esz,
+        "zfwd": (nf * sa + rk_arrays * ns * sc) * esz,
     }
 
 
@@ -154,6 +157,32 @@ def run_mhd(pst, torch, I, n=1024, steps=5, warmup=1):
     res = {"n": n, "precision": "fp32", "rk_order": 2, "steps": steps, "ms_per_step": ms,
            "median_step_ms": float(np.median(per)), "kernels": kern,
            "effective_GB_s": 2 * sum(kb.values()) / ms / 1e6, "energy_end": plan.energy()}
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_boussinesq(pst, torch, I, n=512, steps=10, warmup=2):
+    """Boussinesq 512^3 FP32 RK4 (the paper's reference equations), nu = kappa
+    = 2e-3, N = 2, dt = 5e-4: the Navier-Stokes workload's u and forcing plus a
+    random-phase theta of the same spectrum (variance 1/2): ms per step and per pass."""
+    plan = pst.Plan(n, solver="boussinesq", precision="fp32", rk_order=4, nu=2e-3, kappa=2e-3, dt=5e-4,
+                    nbv=2.0, timers=True)
+    plan.set_state(I.random_solenoidal(n, 1, dtype=np.complex64), field="u")
+    plan.set_state(I.random_scalar(n, 2, energy=0.5, dtype=np.complex64), field="theta")
+    plan.set_forcing(I.forcing_shells(n, 1, dtype=np.complex64))
+    plan.step(warmup)
+    torch.cuda.synchronize()
+    plan.timers(reset=True)
+    ms, per = timed_steps(plan, torch, steps)
+    tm = plan.timers(reset=True)
+    kb = kernel_bytes(n, 8, 4, bq=True)
+    kern = {k: {"ms": tm[k][0] / max(tm[k][1], 1), "launches": tm[k][1]} for k in KINDS}
+    for k in KINDS:
+        kern[k]["GB_s"] = kb[k] / kern[k]["ms"] / 1e6
+    res = {"n": n, "precision": "fp32", "rk_order": 4, "nbv": 2.0, "steps": steps, "ms_per_step": ms,
+           "median_step_ms": float(np.median(per)), "kernels": kern,
+           "effective_GB_s": 4 * sum(kb.values()) / ms / 1e6, "energy_end": plan.energy()}
     plan.close()
     torch.cuda.empty_cache()
     return res
@@ -389,6 +418,9 @@ def main():
     if not a.no_mhd:
         print("[bench] MHD 1024^3 FP32 RK2 (5 steps)", file=sys.stderr, flush=True)
         out_extra["mhd1024"] = run_mhd(pst, torch, I)
+    if not a.no_bq and n == 512:
+        print("[bench] Boussinesq 512^3 FP32 RK4 (10 steps)", file=sys.stderr, flush=True)
+        out_extra["boussinesq512"] = run_boussinesq(pst, torch, I)
     if not a.no_fno:
         print("[bench] FNO surrogate forward / training step (64^3, batch 8)", file=sys.stderr, flush=True)
         out_extra["fno"] = run_fno(pst, torch, I)

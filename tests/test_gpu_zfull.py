@@ -14,6 +14,9 @@ benchmark times (collected after the other GPU tests: these are the slow ones).
   in host memory): right-hand side of the FP32 and FP64 paths against the
   oracle, and one RK2 step of the 1024^3 benchmark's parameters at 128^3; the
   Navier-Stokes right-hand side at 256^3 (its own radix schedule).
+* Boussinesq 512^3, RK4, dt = 5e-4, nu = kappa = 2e-3, N = 2, shell forcing
+  (the benchmark's Boussinesq leg): one right-hand side and one RK4 step of
+  the FP32 and FP64 paths against the FP64 oracle, every coefficient.
 * The 96-run ensemble (32 x 48^3, 48 x 64^3, 16 x 96^3) with its autotuned
   schedule: the graph-replayed persistent step equals the batched launches
   bitwise for every run, and one run of each size equals the oracle.
@@ -259,6 +262,40 @@ def test_ns_rhs_256(O, P, torch, prec):
     got = rd.cpu().numpy()
     assert max(rel(got[c], ref[c]) for c in range(3)) < TOL[prec]
     plan.close()
+
+
+# ------------------------------------------------------------ Boussinesq 512^3
+@pytest.fixture(scope="module")
+def bq512(O):
+    u = I.random_solenoidal(N512, 1)
+    t = I.random_scalar(N512, 2, energy=0.5)
+    f = I.forcing_shells(N512, 1)
+    rhs = O.bq_rhs(u, t, 2.0, fhat=f)
+    step = O.step(u, 1, dt=DT512, nu=NU512, rk=4, fhat=f, theta=t, kappa=NU512, nbv=2.0)
+    return u, t, f, rhs, step
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_bq512_rhs_and_step(P, torch, bq512, prec):
+    u, t, f, (ru, rt), (su, stt) = bq512
+    plan = P.Plan(N512, solver="boussinesq", precision=prec, rk_order=4, nu=NU512, kappa=NU512, dt=DT512, nbv=2.0)
+    plan.set_forcing(f)
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    sd = torch.from_numpy(np.concatenate([u, t[None]])).to(ct).cuda()
+    rd = torch.empty_like(sd)
+    plan.rhs(sd, rd)
+    got = rd.cpu().numpy()
+    assert max(rel(got[c], ru[c]) for c in range(3)) < TOL[prec]
+    assert rel(got[3], rt) < TOL[prec]
+    del rd
+    plan.set_state(sd[:3], field="u")
+    plan.set_state(sd[3:], field="theta")
+    del sd
+    plan.step(1)
+    assert max(rel(plan.get_state("u")[c], su[c]) for c in range(3)) < TOL[prec]
+    assert rel(plan.get_state("theta")[0], stt) < TOL[prec]
+    plan.close()
+    torch.cuda.empty_cache()
 
 
 # ------------------------------------------------------------ ensemble, 96 runs
