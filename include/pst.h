@@ -222,7 +222,8 @@ enum {
     PST_ENS_PERSISTENT_GRAPH = 0, /* persistent step kernel replayed from a HIP graph (default) */
     PST_ENS_PERSISTENT = 1,       /* persistent step kernel, launched directly */
     PST_ENS_BATCHED = 2,          /* one launch per (pass, grid size) covering all runs of that size */
-    PST_ENS_SEQUENTIAL = 3        /* one launch per (pass, run) */
+    PST_ENS_SEQUENTIAL = 3,       /* one launch per (pass, run) */
+    PST_ENS_BATCHED_GRAPH = 4     /* the batched launches of one step replayed from a HIP graph */
 };
 
 /* Create nruns runs; run r has grid n[r] (each of 32, 48, 64, 96; at most 4
@@ -244,6 +245,8 @@ pst_status pst_ensemble_get_state(pst_ensemble *ens, int run, void *uhat, int me
  * synchronise the stream and return HIP if a device-wide barrier timed out. */
 pst_status pst_ensemble_step(pst_ensemble *ens, int nsteps);
 pst_status pst_ensemble_set_mode(pst_ensemble *ens, int mode);
+/* Current mode (PST_ENS_*), e.g. the one pst_ensemble_autotune picked. */
+pst_status pst_ensemble_get_mode(const pst_ensemble *ens, int *mode);
 
 /* Energy of every run (double[nruns]).  Synchronous. */
 pst_status pst_ensemble_energy(pst_ensemble *ens, double *per_run);
@@ -261,10 +264,13 @@ pst_status pst_ensemble_diagnostics(pst_ensemble *ens, double *energy, double *e
 pst_status pst_ensemble_rel_l2(pst_ensemble *a, const pst_ensemble *b, double *per_run);
 
 /* Pick the schedule variant (radix order x tile lines) by timing each on
- * persistent steps (the state is saved and restored around the timing).
- * cache_path (may be NULL) is a JSON object keyed by device architecture,
- * precision, RK order and the run sizes; a cached choice is reused unless
- * force != 0.  *chosen (may be NULL) receives the variant. */
+ * persistent steps (the state is saved and restored around the timing); then,
+ * if the ensemble is in one of the two graph modes, switch it to whichever of
+ * PERSISTENT_GRAPH and BATCHED_GRAPH steps faster (every mode gives bitwise
+ * the same states).  cache_path (may be NULL) is a JSON object keyed by device
+ * architecture, precision, RK order and the run sizes (the mode under the key
+ * with "/mode" appended); cached choices are reused unless force != 0.
+ * *chosen (may be NULL) receives the variant. */
 pst_status pst_ensemble_autotune(pst_ensemble *ens, const char *cache_path, int force, int *chosen);
 pst_status pst_ensemble_set_schedule(pst_ensemble *ens, int variant);
 

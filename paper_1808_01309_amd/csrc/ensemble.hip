@@ -8,7 +8,9 @@
 //                         units of all runs for each pass of every RK stage,
 //                         with a device-wide barrier between passes;
 //   2 BATCHED             one launch per (pass, class) covering all its runs;
-//   3 SEQUENTIAL          one launch per (pass, run).
+//   3 SEQUENTIAL          one launch per (pass, run);
+//   4 BATCHED + GRAPH     the batched launches of one step captured once in a
+//                         HIP graph and replayed every step.
 // The schedule variant (radix order x tile lines) is picked by timing the
 // candidates (pst_ensemble_autotune) and cached.  FP32 only.
 #include <math.h>
@@ -314,7 +316,7 @@ static void launch_step(pst_ensemble* E) {
     for (int s = 0; s < d.nstages; ++s)
         for (int pass = 0; pass < 5; ++pass)
             for (int c = 0; c < d.ncls; ++c) {
-                if (E->mode == 2) K->launch_pass(d.cls[c], pass, s > 0, d.modes[s], d.h, E->stream);
+                if (E->mode == 2 || E->mode == 4) K->launch_pass(d.cls[c], pass, s > 0, d.modes[s], d.h, E->stream);
                 else
                     for (int r = 0; r < d.cls[c].nruns; ++r)
                         K->launch_pass_run(d.cls[c], pass, s > 0, d.modes[s], d.h, r, E->stream);
@@ -520,9 +522,15 @@ static pst_status check_err_flag(pst_ensemble* E) {
 
 extern "C" pst_status pst_ensemble_set_mode(pst_ensemble* E, int mode) {
     if (!E) return PST_ERR_INVALID_ARG;
-    if (mode < 0 || mode > 3) return efail(E, PST_ERR_INVALID_ARG, "mode %d", mode);
+    if (mode < 0 || mode > 4) return efail(E, PST_ERR_INVALID_ARG, "mode %d", mode);
     drop_graph(E);
     E->mode = mode;
+    return PST_OK;
+}
+
+extern "C" pst_status pst_ensemble_get_mode(const pst_ensemble* E, int* mode) {
+    if (!E || !mode) return PST_ERR_INVALID_ARG;
+    *mode = E->mode;
     return PST_OK;
 }
 
@@ -530,7 +538,7 @@ extern "C" pst_status pst_ensemble_step(pst_ensemble* E, int nsteps) {
     if (!E) return PST_ERR_INVALID_ARG;
     if (nsteps < 0) return efail(E, PST_ERR_INVALID_ARG, "nsteps < 0");
     if (nsteps == 0) return PST_OK;
-    if (E->mode == 0) {  // persistent kernel replayed from a captured graph
+    if (E->mode == 0 || E->mode == 4) {  // one step's launches replayed from a captured graph
         if (!E->graph_valid) {
             hipStream_t cs = nullptr;
             if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
@@ -635,9 +643,12 @@ extern "C" pst_status pst_ensemble_autotune(pst_ensemble* E, const char* cache_p
     for (size_t c = 0; c < E->cls.size(); ++c)
         key += (c ? "-" : "") + std::to_string(E->cls[c].n) + "x" + std::to_string(E->cls[c].runs.size());
     std::map<std::string, int> cache = read_cache(cache_path);
+    const std::string mkey = key + "/mode";
+    const bool graph_mode = E->mode == 0 || E->mode == 4;
     if (!force && cache.count(key) && cache[key] >= 0 && cache[key] < ENS_NVAR) {
         drop_graph(E);
         E->var = cache[key];
+        if (graph_mode && cache.count(mkey) && (cache[mkey] == 0 || cache[mkey] == 4)) E->mode = cache[mkey];
         if (chosen) *chosen = E->var;
         return PST_OK;
     }
@@ -676,14 +687,43 @@ extern "C" pst_status pst_ensemble_autotune(pst_ensemble* E, const char* cache_p
             bestv = v;
         }
     }
+    // the graph modes with that variant: one persistent launch per step against
+    // the batched launches, each replayed from its graph
+    int mode_pick = saved_mode;
+    if (st == PST_OK && graph_mode) {
+        E->var = bestv;
+        float tbest = 1e30f;
+        for (int m : {0, 4}) {
+            E->mode = m;
+            drop_graph(E);
+            st = pst_ensemble_step(E, 1);  // captures the graph, warms up
+            if (st != PST_OK) break;
+            hipEventRecord(a, E->stream);
+            for (int it = 0; it < 3; ++it) hipGraphLaunch(E->gexec, E->stream);
+            hipEventRecord(b, E->stream);
+            if (hipEventSynchronize(b) != hipSuccess) {
+                st = efail(E, PST_ERR_HIP, "autotune timing failed");
+                break;
+            }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, a, b);
+            if (m == 0) st = check_err_flag(E);
+            if (st == PST_OK && ms < tbest) {
+                tbest = ms;
+                mode_pick = m;
+            }
+        }
+        drop_graph(E);
+    }
     hipEventDestroy(a);
     hipEventDestroy(b);
     for (size_t c = 0; c < E->cls.size(); ++c)
         hipMemcpy(E->cls[c].U, saved[c].data(), saved[c].size(), hipMemcpyHostToDevice);
-    E->mode = saved_mode;
+    E->mode = mode_pick;
     E->var = bestv;
     if (st != PST_OK) return st;
     cache[key] = bestv;
+    if (graph_mode) cache[mkey] = mode_pick;
     write_cache(cache_path, cache);
     if (chosen) *chosen = bestv;
     return PST_OK;

@@ -78,6 +78,7 @@ for _name, _args in [("pst_set_state", [_P, _I, _I, _P, _I]), ("pst_get_state", 
 _ens_sigs = [("pst_ensemble_create", [_I, _P, ctypes.POINTER(pst_params), _P, ctypes.POINTER(_P)]),
              ("pst_ensemble_set_state", [_P, _I, _P, _I]), ("pst_ensemble_get_state", [_P, _I, _P, _I]),
              ("pst_ensemble_step", [_P, _I]), ("pst_ensemble_set_mode", [_P, _I]),
+             ("pst_ensemble_get_mode", [_P, _P]),
              ("pst_ensemble_energy", [_P, _P]), ("pst_ensemble_autotune", [_P, ctypes.c_char_p, _I, _P]),
              ("pst_ensemble_set_schedule", [_P, _I]), ("pst_ensemble_query", [_P, _P, _P, _P, _P, _P]),
              ("pst_ensemble_project", [_P]), ("pst_ensemble_diagnostics", [_P, _P, _P]),
@@ -113,7 +114,8 @@ EXPORTED = ["pst_fno_create", "pst_fno_destroy", "pst_fno_last_error", "pst_fno_
             "pst_fno_get_params", "pst_fno_get_grad", "pst_fno_forward", "pst_fno_loss_grad", "pst_fno_adam",
             "pst_fno_train_step",
             "pst_ensemble_create", "pst_ensemble_destroy", "pst_ensemble_last_error", "pst_ensemble_set_state",
-            "pst_ensemble_get_state", "pst_ensemble_step", "pst_ensemble_set_mode", "pst_ensemble_energy",
+            "pst_ensemble_get_state", "pst_ensemble_step", "pst_ensemble_set_mode", "pst_ensemble_get_mode",
+            "pst_ensemble_energy",
             "pst_ensemble_autotune", "pst_ensemble_set_schedule", "pst_ensemble_query", "pst_ensemble_project",
             "pst_ensemble_diagnostics", "pst_ensemble_rel_l2",
             "pst_status_str", "pst_last_error", "pst_supported_n", "pst_plan_create", "pst_plan_destroy",
@@ -297,7 +299,7 @@ def _np_dtype(x):
             torch.float32: np.float32, torch.float64: np.float64}[x.dtype]
 
 
-ENS_MODES = {"graph": 0, "persistent": 1, "batched": 2, "sequential": 3}
+ENS_MODES = {"graph": 0, "persistent": 1, "batched": 2, "sequential": 3, "batched_graph": 4}
 
 
 class Ensemble:
@@ -377,6 +379,11 @@ class Ensemble:
 
     def set_schedule(self, variant):
         self._check(lib.pst_ensemble_set_schedule(self._h, variant))
+
+    def get_mode(self):
+        m = ctypes.c_int(-1)
+        self._check(lib.pst_ensemble_get_mode(self._h, ctypes.byref(m)))
+        return {v: k for k, v in ENS_MODES.items()}.get(m.value, m.value)
 
     def query(self):
         nc = ctypes.c_int()

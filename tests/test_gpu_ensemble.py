@@ -52,7 +52,7 @@ def run_mode(P, init, mode, variant=None):
     return out, e
 
 
-@pytest.mark.parametrize("mode", ["graph", "persistent", "batched", "sequential"])
+@pytest.mark.parametrize("mode", ["graph", "persistent", "batched", "sequential", "batched_graph"])
 def test_modes_match_oracle(O, P, init, ref, mode):
     out, e = run_mode(P, init, mode)
     for r in range(len(SIZES)):
@@ -65,8 +65,9 @@ def test_modes_bitwise_equal(P, init):
     a, _ = run_mode(P, init, "graph")
     b, _ = run_mode(P, init, "sequential")
     c, _ = run_mode(P, init, "batched")
+    d, _ = run_mode(P, init, "batched_graph")
     for r in range(len(SIZES)):
-        assert np.array_equal(a[r], b[r]) and np.array_equal(a[r], c[r])
+        assert np.array_equal(a[r], b[r]) and np.array_equal(a[r], c[r]) and np.array_equal(a[r], d[r])
 
 
 @pytest.mark.parametrize("variant", [1, 2, 3])
@@ -77,11 +78,13 @@ def test_variants_match_oracle(P, init, ref, variant):
 
 
 def test_graph_replay_many_steps(O, P):
-    """Replaying the captured step 20 times equals 20 directly launched steps."""
+    """Replaying a captured step 20 times (persistent or batched graph, with
+    host work and a synchronisation between replays) equals 20 directly
+    launched steps."""
     sizes = [48, 64]
     init = [I.random_solenoidal(n, 7 + n) for n in sizes]
     outs = []
-    for mode in ("graph", "persistent"):
+    for mode in ("graph", "persistent", "batched_graph"):
         ens = P.Ensemble(sizes, rk_order=4, nu=NU, dt=DT)
         ens.set_mode(mode)
         for r, u in enumerate(init):
@@ -92,7 +95,7 @@ def test_graph_replay_many_steps(O, P):
         outs.append([ens.get_state(r) for r in range(2)])
         ens.close()
     for r in range(2):
-        assert np.array_equal(outs[0][r], outs[1][r])
+        assert np.array_equal(outs[0][r], outs[1][r]) and np.array_equal(outs[0][r], outs[2][r])
     ref = O.step(init[0], 20, dt=DT, nu=NU, rk=4)
     assert rel(outs[0][0], ref) < 1e-5
 
@@ -109,10 +112,16 @@ def test_autotune_and_cache(P, init, tmp_path):
     for r in range(len(SIZES)):
         assert np.array_equal(ens.get_state(r), before[r])
     cache = json.load(open(path))
-    assert list(cache.values()) == [v]
+    keys = sorted(cache)
+    assert len(keys) == 2 and keys[1] == keys[0] + "/mode"
+    assert cache[keys[0]] == v
+    # the default (graph) ensemble is switched to the faster graph mode
+    mode = ens.get_mode()
+    assert mode in ("graph", "batched_graph") and cache[keys[1]] == {"graph": 0, "batched_graph": 4}[mode]
     assert ens.query()["variant"] == v
     ens2 = P.Ensemble(SIZES, rk_order=RK, nu=NU, dt=DT)
     assert ens2.autotune(path) == v        # served from the cache
+    assert ens2.get_mode() == mode
     assert ens2.query()["sizes"] == [96, 64, 48, 32]
     assert ens2.query()["runs"] == [1, 1, 2, 2]
 
