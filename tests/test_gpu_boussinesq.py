@@ -83,6 +83,24 @@ def test_bq_steps(O, P, torch, prec, rk):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_bq_rhs_sphere(O, P, torch, prec):
+    """Spherical truncation: the nonlinear and coupling terms of u and theta are
+    kept for |k|^2 <= K^2 only (inputs inside the sphere on both sides)."""
+    n = 48
+    u, t = fields(n, 9)
+    kx, ky, kz = I.wavenumbers(n)
+    K = I.kcut_23(n)
+    inside = (kx ** 2 + ky ** 2 + kz ** 2) <= K * K
+    u, t = u * inside[None], t * inside
+    plan = P.Plan(n, solver="boussinesq", precision=prec, nbv=NBV, dealias="sphere")
+    got = gpu_rhs(P, torch, plan, u, t)
+    ru, rt = O.bq_rhs(u, t, NBV, sphere=True)
+    assert max(rel(got[c], ru[c]) for c in range(3)) < TOL[prec]
+    assert rel(got[3], rt) < TOL[prec]
+    plan.close()
+
+
 def test_gravity_wave_gpu(P, torch):
     """The internal gravity wave's amplitudes follow the RK4 stability
     function of the buoyancy rotation (FP64, closed form)."""
