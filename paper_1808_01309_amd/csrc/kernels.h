@@ -412,12 +412,14 @@ template <typename T, class CF, bool MHD> constexpr bool xpass_pp() {
     return !MHD && 2 * tile_lds<T, CF, CF::G * CF::TL>() * (int)sizeof(cx<T>) <= 160 * 1024;
 }
 
-// Tiles per workgroup: FP64 Navier-Stokes loops over 32 consecutive tiles,
-// which overlaps one tile's final stores with the next tile's first reads
-// (measured 11% faster at 512^3); the FP32 body needs every register of its
-// 1024-thread block and spills inside such a loop, so it takes one tile.
+// Tiles per workgroup: FP64, and the half-height FP32 tiles (Boussinesq, and
+// n = 1024), loop over 32 consecutive tiles, which overlaps one tile's final
+// stores with the next tile's first reads (measured 11% faster for FP64
+// Navier-Stokes and the FP32 Boussinesq x pass at 512^3); the 16-line FP32 body
+// needs every register of its 1024-thread block and spills inside such a
+// loop, so it takes one tile.
 template <typename T, class CF, bool MHD> constexpr int xpass_per() {
-    return (sizeof(T) == 8 && xpass_pp<T, CF, MHD>()) ? 32 : 1;
+    return ((sizeof(T) == 8 || CF::TL < tile_lines<T>()) && xpass_pp<T, CF, MHD>()) ? 32 : 1;
 }
 
 template <typename T, class CF, int SYS>
