@@ -16,7 +16,8 @@ benchmark times (collected after the other GPU tests: these are the slow ones).
   Navier-Stokes right-hand side at 256^3 (its own radix schedule).
 * Boussinesq 512^3, RK4, dt = 5e-4, nu = kappa = 2e-3, N = 2, shell forcing
   (the benchmark's Boussinesq leg): one right-hand side and one RK4 step of
-  the FP32 and FP64 paths against the FP64 oracle, every coefficient.
+  the FP32 and FP64 paths against the FP64 oracle, every coefficient; the
+  right-hand side at 256^3; at 1024^3 the internal gravity wave in closed form.
 * The 96-run ensemble (32 x 48^3, 48 x 64^3, 16 x 96^3) with its autotuned
   schedule: the graph-replayed persistent step equals the batched launches
   bitwise for every run, and one run of each size equals the oracle.
@@ -94,7 +95,7 @@ def embed(torch, small, n, kb):
     on any grid)."""
     m = small.shape[1]
     s = torch.from_numpy(small).cuda()
-    big = torch.zeros((3, n, n, n // 2 + 1), dtype=s.dtype, device="cuda")
+    big = torch.zeros((small.shape[0], n, n, n // 2 + 1), dtype=s.dtype, device="cuda")
     for bz, sz in ((slice(0, kb + 1), slice(0, kb + 1)), (slice(n - kb, n), slice(m - kb, m))):
         for by, sy in ((slice(0, kb + 1), slice(0, kb + 1)), (slice(n - kb, n), slice(m - kb, m))):
             big[:, bz, by, :kb + 1] = s[:, sz, sy, :kb + 1]
@@ -295,6 +296,64 @@ def test_bq512_rhs_and_step(P, torch, bq512, prec):
     assert max(rel(plan.get_state("u")[c], su[c]) for c in range(3)) < TOL[prec]
     assert rel(plan.get_state("theta")[0], stt) < TOL[prec]
     plan.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_bq_rhs_256(O, P, torch, prec):
+    n = 256
+    if ("bq", n) not in _mid:
+        u = I.random_solenoidal(n, 50)
+        t = I.random_scalar(n, 51, energy=0.5)
+        f = I.forcing_shells(n, 50)
+        _mid[("bq", n)] = (u, t, f) + tuple(O.bq_rhs(u, t, 2.0, fhat=f))
+    u, t, f, ru, rt = _mid[("bq", n)]
+    plan = P.Plan(n, solver="boussinesq", precision=prec, nbv=2.0)
+    plan.set_forcing(f)
+    ct = torch.complex128 if prec == "fp64" else torch.complex64
+    sd = torch.from_numpy(np.concatenate([u, t[None]])).to(ct).cuda()
+    rd = torch.empty_like(sd)
+    plan.rhs(sd, rd)
+    got = rd.cpu().numpy()
+    assert max(rel(got[c], ru[c]) for c in range(3)) < TOL[prec]
+    assert rel(got[3], rt) < TOL[prec]
+    plan.close()
+
+
+def test_bq_1024_gravity_wave(P, torch):
+    """Boussinesq at 1024^3 (its own radix schedules and tiles): two RK4 steps
+    of the internal gravity wave follow the RK4 stability function of the
+    buoyancy rotation, and every other coefficient stays zero."""
+    n, k, nbv, nu, dt, ns = N1024, (1, 1, 2), 2.5, 1e-3, 0.02, 2
+    u0, t0 = I.gravity_wave_spec(16, k=k, amp_u=0.1, amp_t=0.07)
+    plan = P.Plan(n, solver="boussinesq", precision="fp32", rk_order=4, nu=nu, kappa=nu, dt=dt, nbv=nbv)
+    plan.set_state(embed(torch, u0.astype(np.complex64), n, 2), field="u")
+    th = embed(torch, t0[None].astype(np.complex64), n, 2)
+    plan.set_state(th, field="theta")
+    plan.step(ns)
+    kv = np.array(k, float)
+    k2 = float(kv @ kv)
+    w = nbv * np.sqrt(kv[0] ** 2 + kv[1] ** 2) / np.sqrt(k2)
+    z = 1j * w * dt
+    g = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    A, T = 0.1, 0.07
+    d = np.exp(-nu * k2 * dt)
+    for _ in range(ns):
+        A, T = d * (g.real * A - g.imag * T), d * (g.imag * A + g.real * T)
+    e = u0[:, k[2], k[1], k[0]] / 0.1
+    su = torch.empty((3, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    plan.get_state("u", out=su)
+    got_u = su[:, k[2], k[1], k[0]].cpu().numpy()
+    assert np.abs(got_u - A * e).max() < 1e-6
+    su[:, k[2], k[1], k[0]] = 0
+    assert su.abs().max().item() < 1e-6
+    del su
+    plan.get_state("theta", out=th)
+    assert abs(th[0, k[2], k[1], k[0]].item() - T) < 1e-6
+    th[0, k[2], k[1], k[0]] = 0
+    assert th.abs().max().item() < 1e-6
+    plan.close()
+    del th
     torch.cuda.empty_cache()
 
 
