@@ -191,8 +191,11 @@ __device__ __forceinline__ void lds_sync() {
 // One n-point transform of one line; the caller has loaded v[e] = x[first_pos(g, e)]
 // and receives v[e] = X[last_pos(g, e)].  Every thread of the block (WS: of the
 // wavefront) must call it: it synchronises between stages with lds_sync<WS>.
-template <typename T, class P, int G, bool INV, bool REV = false, bool WS = false>
+// TWC (FP32 only): twiddle factors evaluated in registers by the hardware
+// sine / cosine of the angle in revolutions instead of read from the table.
+template <typename T, class P, int G, bool INV, bool REV = false, bool WS = false, bool TWC = false>
 struct Fft {
+    static_assert(!TWC || sizeof(T) == 4, "computed twiddles are FP32 only");
     static constexpr int N = P::N;
     static constexpr int S = P::S;
     static constexpr int E = N / G;
@@ -224,7 +227,13 @@ struct Fft {
                 const int j = b % NS;
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    cx<T> w = tw[j * r * (N / (NS * R))];
+                    cx<T> w;
+                    if constexpr (TWC) {
+                        const float a = (float)(j * r * (N / (NS * R))) * (1.0f / (float)N);
+                        w = {__builtin_amdgcn_cosf(a), -__builtin_amdgcn_sinf(a)};
+                    } else {
+                        w = tw[j * r * (N / (NS * R))];
+                    }
                     if (INV) w.y = -w.y;
                     v[i * R + r] = cmul(v[i * R + r], w);
                 }

@@ -283,8 +283,8 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
                                            cx<T>* sm, T nbv = T(0)) {
     constexpr bool MHD = SYS == 1, BQ = SYS == 2;
     constexpr int N = CF::N, G = CF::G, TL = CF::TL, TLP = TL + 1, TT = G * TL, SG = NT / TT;
-    using FI = Fft<T, typename CF::P, G, true, false>;
-    using FF = Fft<T, typename CF::P, G, false, true>;
+    using FI = Fft<T, typename CF::P, G, true, false, false, sizeof(T) == 4>;
+    using FF = Fft<T, typename CF::P, G, false, true, false, sizeof(T) == 4>;
     constexpr int E = FI::E, NTZ = ztiles<N, TL>();
     constexpr int NP = MHD ? 6 : BQ ? 5 : 3;   // backward pairs
     constexpr int NO = MHD ? 3 : 2;            // forward packed lines
