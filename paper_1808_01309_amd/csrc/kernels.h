@@ -132,7 +132,7 @@ __device__ __forceinline__ void zinv_body(const cx<T>* __restrict__ st, cx<T>* _
     // A line's G threads are lanes of one wavefront: the FP64 transforms
     // synchronise per wavefront (measured faster there; FP32 keeps the
     // workgroup barrier, which measured slightly faster for it).
-    using F = Fft<T, typename CF::P, G, true, false, sizeof(T) == 8 && G <= 64>;
+    using F = Fft<T, typename CF::P, G, true, false, sizeof(T) == 8 && G <= 64, sizeof(T) == 4>;
     constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
     const int l = tid / G, g = tid % G;
     const int64_t line = unit * LPB + l;
@@ -229,7 +229,7 @@ __device__ __forceinline__ void ypass_body(const cx<T>* __restrict__ in, cx<T>* 
                                            const cx<T>* __restrict__ tw, const Geo& geo, int64_t fs_in,
                                            int64_t fs_out, int nf, int64_t unit, int tid, cx<T>* sm) {
     constexpr int N = CF::N, G = CF::G, TL = CF::TL, TLP = TL + 1, TT = G * TL, SG = NT / TT;
-    using F = Fft<T, typename CF::P, G, INV>;
+    using F = Fft<T, typename CF::P, G, INV, false, false, sizeof(T) == 4>;
     constexpr int E = F::E, NTZ = ztiles<N, TL>();
     const int s = tid / TT, r = tid % TT;
     const int t = r % TL, g = r / TL;
@@ -493,7 +493,7 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
                                            cx<T>* __restrict__ Acc, cx<T>* __restrict__ R, int mode, int64_t unit,
                                            int tid, cx<T>* sm) {
     constexpr int N = CF::N, G = CF::G;
-    using F = Fft<T, typename CF::P, G, false>;
+    using F = Fft<T, typename CF::P, G, false, false, false, sizeof(T) == 4>;
     constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
     constexpr bool MHD = SYS == 1, BQ = SYS == 2;
     constexpr int NF = MHD ? 6 : BQ ? 4 : 3;
