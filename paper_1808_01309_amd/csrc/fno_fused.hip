@@ -78,7 +78,7 @@ template <int N>
 __device__ __forceinline__ void rows_r2c(const float* X, int W, int m, const RowBlock& rb, cx<float>* __restrict__ t1,
                                          const cx<float>* __restrict__ tw, cx<float>* fl) {
     using C = NCfg<N>;
-    using F = Fft<float, typename C::P, C::G, false>;
+    using F = Fft<float, typename C::P, C::G, false, false, false, true>;
     constexpr int G = C::G, E = F::E, NPG = FT / G, LS = LineLds<float>::size(N), PB = fno_rows<N>() * N;
     const int g = threadIdx.x % G, li = threadIdx.x / G;
     const LineLds<float> lds{fl + li * LS};
@@ -115,7 +115,7 @@ template <int N>
 __device__ __forceinline__ void rows_c2r(const cx<float>* __restrict__ t1, int W, int m, const RowBlock& rb, float* X,
                                          const cx<float>* __restrict__ tw, cx<float>* fl) {
     using C = NCfg<N>;
-    using F = Fft<float, typename C::P, C::G, true>;
+    using F = Fft<float, typename C::P, C::G, true, false, false, true>;
     constexpr int G = C::G, E = F::E, NPG = FT / G, LS = LineLds<float>::size(N), PB = fno_rows<N>() * N;
     const int g = threadIdx.x % G, li = threadIdx.x / G;
     const LineLds<float> lds{fl + li * LS};

@@ -596,7 +596,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(LINE_BLOCK) void k_fftx_r2c(const T* __restrict__ in, cx<T>* __restrict__ out,
                                                           const cx<T>* __restrict__ tw, int64_t npairs) {
     using C = NCfg<N>;
-    using F = Fft<T, typename C::P, C::G, false>;
+    using F = Fft<T, typename C::P, C::G, false, false, false, sizeof(T) == 4>;
     constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N), NXH = N / 2 + 1;
     __shared__ cx<T> sm[LPB * LS];
     const int l = threadIdx.x / G, g = threadIdx.x % G;
@@ -628,7 +628,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(LINE_BLOCK) void k_fftx_c2r(const cx<T>* __restrict__ in, T* __restrict__ out,
                                                           const cx<T>* __restrict__ tw, int64_t npairs) {
     using C = NCfg<N>;
-    using F = Fft<T, typename C::P, C::G, true>;
+    using F = Fft<T, typename C::P, C::G, true, false, false, sizeof(T) == 4>;
     constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N), NXH = N / 2 + 1;
     __shared__ cx<T> sm[LPB * LS];
     const int l = threadIdx.x / G, g = threadIdx.x % G;
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(NCfg<N>::G * tile_lines<T>()) void k_fft_strided(co
                                                                               int64_t rs, int64_t ncols, int64_t ps,
                                                                               T scale) {
     using C = NCfg<N>;
-    using F = Fft<T, typename C::P, C::G, INV>;
+    using F = Fft<T, typename C::P, C::G, INV, false, false, sizeof(T) == 4>;
     constexpr int G = C::G, E = F::E, TL = tile_lines<T>(), TLP = TL + 1;
     __shared__ cx<T> sm[N * TLP];
     const int t = threadIdx.x % TL, g = threadIdx.x / TL;
@@ -715,7 +715,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(LINE_BLOCK) void k_fftx_r2c_m(const T* __restrict__ in, cx<T>* __restrict__ out,
                                                             const cx<T>* __restrict__ tw, int64_t npairs, int m) {
     using C = NCfg<N>;
-    using F = Fft<T, typename C::P, C::G, false>;
+    using F = Fft<T, typename C::P, C::G, false, false, false, sizeof(T) == 4>;
     constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N);
     __shared__ cx<T> sm[LPB * LS];
     const int l = threadIdx.x / G, g = threadIdx.x % G;
@@ -747,7 +747,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(LINE_BLOCK) void k_fftx_c2r_m(const cx<T>* __restrict__ in, T* __restrict__ out,
                                                             const cx<T>* __restrict__ tw, int64_t npairs, int m) {
     using C = NCfg<N>;
-    using F = Fft<T, typename C::P, C::G, true>;
+    using F = Fft<T, typename C::P, C::G, true, false, false, sizeof(T) == 4>;
     constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N);
     __shared__ cx<T> sm[LPB * LS];
     const int l = threadIdx.x / G, g = threadIdx.x % G;
@@ -792,7 +792,7 @@ __global__ __launch_bounds__(NCfg<N>::G * tile_lines<T>()) void k_fft_cols_m(
     const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw, int64_t ncols, int64_t rs_in,
     int64_t ps_in, int64_t rs_out, int64_t ps_out, int m, T scale) {
     using C = NCfg<N>;
-    using F = Fft<T, typename C::P, C::G, INV>;
+    using F = Fft<T, typename C::P, C::G, INV, false, false, sizeof(T) == 4>;
     constexpr int G = C::G, E = F::E, TL = tile_lines<T>(), TLP = TL + 1;
     __shared__ cx<T> sm[N * TLP];
     const int t = threadIdx.x % TL, g = threadIdx.x / TL;
