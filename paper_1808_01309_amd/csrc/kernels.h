@@ -39,7 +39,11 @@ template <typename T> constexpr int tile_lines() { return sizeof(T) == 4 ? 16 : 
 // formed: MHD (twice the fields) and n = 1024 (twice the points per thread)
 // each halve the tile so the block stays within the register file.
 template <typename T, bool MHD, int N>
-constexpr int xpass_lines() { return tile_lines<T>() / (MHD ? 2 : 1) / (N >= 1024 ? 2 : 1); }
+constexpr int xpass_lines() {
+    // FP32 Navier-Stokes below n = 1024: 8 lines, two workgroups per CU
+    if (sizeof(T) == 4 && !MHD && N < 1024) return 8;
+    return tile_lines<T>() / (MHD ? 2 : 1) / (N >= 1024 ? 2 : 1);
+}
 constexpr int LINE_BLOCK = 256;
 
 // A kernel configuration: radix schedule P (length N), G threads per line,
@@ -412,21 +416,30 @@ template <typename T, class CF, bool MHD> constexpr bool xpass_pp() {
     return !MHD && 2 * tile_lds<T, CF, CF::G * CF::TL>() * (int)sizeof(cx<T>) <= 160 * 1024;
 }
 
-// Tiles per workgroup: FP64, and the half-height FP32 tiles (Boussinesq, and
-// n = 1024), loop over 32 consecutive tiles, which overlaps one tile's final
+// Two workgroups per CU for the FP32 Navier-Stokes x pass below n = 1024: its
+// 8-line tile fits 128 VGPRs, so two tiles are in flight per CU and one's
+// loads overlap the other's transforms (1.52 -> 1.49 ms at 512^3 against one
+// 16-line tile per CU).
+template <typename T, int N, int SYS> constexpr bool xpass_two_per_cu() {
+    return SYS == 0 && sizeof(T) == 4 && N < 1024;
+}
+
+// Tiles per workgroup: FP64 and the other half-height FP32 tiles (Boussinesq,
+// n = 1024) loop over 32 consecutive tiles, which overlaps one tile's final
 // stores with the next tile's first reads (measured 11% faster for FP64
-// Navier-Stokes and the FP32 Boussinesq x pass at 512^3); the 16-line FP32 body
-// needs every register of its 1024-thread block and spills inside such a
-// loop, so it takes one tile.
-template <typename T, class CF, bool MHD> constexpr int xpass_per() {
-    return ((sizeof(T) == 8 || CF::TL < tile_lines<T>()) && xpass_pp<T, CF, MHD>()) ? 32 : 1;
+// Navier-Stokes and the FP32 Boussinesq x pass at 512^3); MHD and the FP32
+// Navier-Stokes tiles below 1024 take one tile (a loop costs them registers
+// and occupancy).
+template <typename T, class CF, int SYS> constexpr int xpass_per() {
+    if constexpr (xpass_two_per_cu<T, CF::N, SYS>()) return 1;
+    else return ((sizeof(T) == 8 || CF::TL < tile_lines<T>()) && xpass_pp<T, CF, SYS == 1>()) ? 32 : 1;
 }
 
 template <typename T, class CF, int SYS>
-__global__ __launch_bounds__((CF::G * CF::TL)) void k_xpass(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
+__global__ __launch_bounds__((CF::G * CF::TL), (xpass_two_per_cu<T, CF::N, SYS>() ? 4 : 1)) void k_xpass(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
                                                           const cx<T>* __restrict__ tw, Geo geo, T nbv) {
     constexpr bool PPB = xpass_pp<T, CF, SYS == 1>();
-    constexpr int PER = xpass_per<T, CF, SYS == 1>();
+    constexpr int PER = xpass_per<T, CF, SYS>();
     __shared__ cx<T> sm[(PPB ? 2 : 1) * tile_lds<T, CF, CF::G * CF::TL>()];
     // each XCD takes a contiguous range of tiles (measured faster, most for the
     // narrow MHD tiles at n = 1024 whose rows share cache lines)
@@ -862,13 +875,13 @@ struct Impl {
         } else if (P->p.solver == PST_BOUSSINESQ) {
             // five backward pairs: the MHD tile (half the lines) keeps them in registers
             using XC = XCfg<T, N, true>;
-            constexpr int per = xpass_per<T, XC, false>();
+            constexpr int per = xpass_per<T, XC, 2>();
             hipLaunchKernelGGL((k_xpass<T, XC, 2>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(), per)),
                                dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
                                (const cx<T>*)P->tw, g, (T)P->p.nbv);
         } else {
             using XC = XCfg<T, N, false>;
-            constexpr int per = xpass_per<T, XC, false>();
+            constexpr int per = xpass_per<T, XC, 0>();
             hipLaunchKernelGGL((k_xpass<T, XC, 0>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(), per)),
                                dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
                                (const cx<T>*)P->tw, g, T(0));
