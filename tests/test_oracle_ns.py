@@ -119,6 +119,76 @@ def test_dealiased_operator_equals_galerkin_sum(O, n):
     assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
 
 
+def galerkin_ns_sets(h, n, r_in, r_out):
+    """D P sum_{p+q=k} uhat(p) x (i q x uhat(q)) by brute force, with p, q over
+    the modes of the input ball |p|^2 <= r_in^2 and the result kept on the
+    ball |k|^2 <= r_out^2 (spherical truncation of radius r_out)."""
+    f = full_spectrum(h, n)
+    ks = np.arange(-(n // 2), n // 2 + 1)
+    ball = np.array([(a, b, c) for a in ks for b in ks for c in ks if a * a + b * b + c * c <= r_in * r_in])
+    uh = np.array([f[:, kz % n, ky % n, kx % n] for kx, ky, kz in ball])
+    wh = 1j * np.cross(ball, uh)
+    index = {tuple(m): i for i, m in enumerate(ball)}
+    out = np.zeros((3, n, n, n // 2 + 1), complex)
+    for a in range(0, r_out + 1):
+        for b in range(-r_out, r_out + 1):
+            for c in range(-r_out, r_out + 1):
+                k = np.array([a, b, c])
+                k2 = int(k @ k)
+                if k2 > r_out * r_out or k2 == 0:
+                    continue
+                acc = np.zeros(3, complex)
+                for j, p in enumerate(ball):
+                    q = tuple(k - p)
+                    if q in index:
+                        acc += np.cross(uh[j], wh[index[q]])
+                acc = acc - k * (k @ acc) / k2
+                out[:, c % n, b % n, a] = acc
+    return out
+
+
+def ball_mask(n, r):
+    kx, ky, kz = I.wavenumbers(n)
+    return (kx ** 2 + ky ** 2 + kz ** 2) <= r * r
+
+
+@pytest.mark.parametrize("n", [9, 12])
+def test_spherical_truncation_equals_galerkin_sum(O, n):
+    """Spherical truncation |k|^2 <= K^2, K = ceil(n/3) - 1 (the ball lies in
+    the alias-free cube, so the pseudospectral operator is exact): for a field
+    on the ball and for a field on the whole cube, the operator equals the
+    brute-force Galerkin sum over the input's modes, kept on the ball.  The
+    ball's surface |k|^2 = K^2 is populated and must be kept (<= not <)."""
+    K = I.kcut_23(n)
+    u_cube = I.random_solenoidal(n, 21, spectrum=lambda k: np.exp(-0.1 * k), kcut=K)
+    u_ball = u_cube * ball_mask(n, K)[None]
+    for u, r_in in ((u_ball, K), (u_cube, int(np.ceil(np.sqrt(3) * K)))):
+        ref = galerkin_ns_sets(u, n, r_in, K)
+        got = O.ns_rhs(u, kcut=K, sphere=True)
+        assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+        # nothing outside the ball; the surface modes carry a nonzero term
+        assert np.abs(got[:, ~ball_mask(n, K)]).max() == 0.0
+        kx, ky, kz = I.wavenumbers(n)
+        surf = (kx ** 2 + ky ** 2 + kz ** 2) == K * K
+        assert np.abs(got[:, surf]).max() > 1e-3 * np.abs(ref).max()
+    # the strict-inequality misreading drops the populated surface
+    ref = galerkin_ns_sets(u_ball, n, K, K)
+    strict = ref * (~surf)[None]
+    assert np.abs(strict - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,r", [(9, 4), (12, 5)])
+def test_spherical_radius_that_aliases(O, n, r):
+    """Negative control: a ball of radius r with 3r >= n (here larger than the
+    cube's cutoff) is not alias-free: the pseudospectral result departs from
+    the Galerkin sum."""
+    u = I.random_solenoidal(n, 22, spectrum=lambda k: np.exp(-0.1 * k), kcut=n // 2 - 1)
+    u = u * ball_mask(n, r)[None]
+    ref = galerkin_ns_sets(u, n, r, r)
+    got = O.ns_rhs(u, kcut=r, sphere=True)
+    assert np.abs(got - ref).max() > 1e-3 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("n", [9, 12])
 def test_third_rule_reading_aliases(O, n):
     """Negative control: keeping |k_i| <= n/3 (3K = n) is not alias-free."""
