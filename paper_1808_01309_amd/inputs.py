@@ -85,27 +85,35 @@ def flat_shells(lo, hi):
 
 
 def random_solenoidal(n, seed, field=0, spectrum=spectrum_c2, energy=1.0, kcut=None,
-                      dtype=np.complex128):
+                      dtype=np.complex128, shape=None, box=None):
     """Random-phase solenoidal field in the library's spectral layout.
 
-    For every stored mode k != 0 inside the cube |k_i| <= kcut:
+    For every stored mode k != 0 inside the cube |k_i| <= kcut_i:
         uhat = A(|k|) (exp(i t1) cos(phi) e1 + exp(i t2) sin(phi) e2),
         e1 = k x z / |k x z|  (x if k is parallel to z),  e2 = k x e1 / |k x e1|,
         A = sqrt(E(|k|) / (4 pi |k|^2)),
-    with t1, t2, phi uniform in [0, 2 pi) from the counter-based generator.
-    On the kx = 0 plane the half with ky > 0 (or ky = 0, kz > 0) is drawn and
-    the other half is its complex conjugate, so the field is real.  |uhat| = A
-    whatever the phases, so the amplitudes are rescaled to the requested
-    energy 1/2 sum_k w |uhat|^2 (w = 1 on kx = 0, else 2) before the phases are
-    applied.  Built one kx plane at a time.
+    with t1, t2, phi uniform in [0, 2 pi) from the counter-based generator
+    (keyed by the integer wavenumbers) and k the physical wavenumber
+    2 pi (p / Lx, q / Ly, r / Lz).  On the kx = 0 plane the half with ky > 0
+    (or ky = 0, kz > 0) is drawn and the other half is its complex conjugate,
+    so the field is real.  |uhat| = A whatever the phases, so the amplitudes
+    are rescaled to the requested energy 1/2 sum_k w |uhat|^2 (w = 1 on
+    kx = 0, else 2) before the phases are applied.  Built one kx plane at a
+    time.  shape = (nx, ny, nz) and box = (Lx, Ly, Lz) give an anisotropic
+    grid (layout [3][nz][ny][nx//2+1]); kcut is then None or a per-axis tuple.
     """
+    nx, ny, nz = (n, n, n) if shape is None else shape
+    al = np.array([1.0, 1.0, 1.0]) if box is None else 2.0 * np.pi / np.asarray(box, float)
     if kcut is None:
-        kcut = kcut_23(n)
-    nxh = n // 2 + 1
-    kxmax = min(kcut, n // 2)
-    out = np.zeros((3, n, n, nxh), dtype)
-    ks = np.arange(-kcut, kcut + 1)
-    kz2, ky2 = np.meshgrid(ks, ks, indexing="ij")
+        kc = (kcut_23(nx), kcut_23(ny), kcut_23(nz))
+    elif np.isscalar(kcut):
+        kc = (kcut,) * 3
+    else:
+        kc = tuple(kcut)
+    nxh = nx // 2 + 1
+    kxmax = min(kc[0], nx // 2)
+    out = np.zeros((3, nz, ny, nxh), dtype)
+    kz2, ky2 = np.meshgrid(np.arange(-kc[2], kc[2] + 1), np.arange(-kc[1], kc[1] + 1), indexing="ij")
     kz2, ky2 = kz2.ravel(), ky2.ravel()
 
     def plane(kx):
@@ -114,8 +122,12 @@ def random_solenoidal(n, seed, field=0, spectrum=spectrum_c2, energy=1.0, kcut=N
             return ky2[keep], kz2[keep]
         return ky2, kz2
 
+    def phys(kx, ky, kz):
+        return al[0] * kx, al[1] * ky, al[2] * kz
+
     def amp2_of(kx, ky, kz):
-        k2 = (kx * kx + ky * ky + kz * kz).astype(np.float64)
+        px, py, pz = phys(kx, ky, kz)
+        k2 = (px * px + py * py + pz * pz).astype(np.float64)
         return spectrum(np.sqrt(k2)) / (4.0 * np.pi * k2)
 
     # a canonical kx > 0 mode has weight 2; a canonical kx = 0 mode stands for
@@ -132,7 +144,7 @@ def random_solenoidal(n, seed, field=0, spectrum=spectrum_c2, energy=1.0, kcut=N
         t1 = 2.0 * np.pi * uniform(seed, field, kxa, ky, kz, 0)
         t2 = 2.0 * np.pi * uniform(seed, field, kxa, ky, kz, 1)
         ph = 2.0 * np.pi * uniform(seed, field, kxa, ky, kz, 2)
-        kvec = np.stack([kxa, ky, kz]).astype(np.float64)
+        kvec = np.stack(phys(kxa, ky, kz)).astype(np.float64)
         # e1 = k x zhat = (ky, -kx, 0), or xhat when k is parallel to zhat
         e1 = np.stack([kvec[1], -kvec[0], np.zeros(ky.shape)])
         par = (kxa == 0) & (ky == 0)
@@ -143,11 +155,56 @@ def random_solenoidal(n, seed, field=0, spectrum=spectrum_c2, energy=1.0, kcut=N
         e2 /= np.sqrt(np.sum(e2 * e2, axis=0))
         coef = (np.exp(1j * t1) * np.cos(ph))[None] * e1 + (np.exp(1j * t2) * np.sin(ph))[None] * e2
         coef *= amp[None]
-        iy, iz = np.mod(ky, n), np.mod(kz, n)
+        iy, iz = np.mod(ky, ny), np.mod(kz, nz)
         for c in range(3):
             out[c, iz, iy, kx] = coef[c]
             if kx == 0:
-                out[c, np.mod(-kz, n), np.mod(-ky, n), 0] = np.conj(coef[c])
+                out[c, np.mod(-kz, nz), np.mod(-ky, ny), 0] = np.conj(coef[c])
+    return out
+
+
+def random_wavefunction(shape, seed, field=5, spectrum=spectrum_c3, number=1.0, condensate=0.0, kcut=None,
+                        box=None, dtype=np.complex128):
+    """Random-phase complex field psi for the Gross-Pitaevskii solver, full
+    spectrum layout [nz][ny][nx] (c2c; no Hermitian symmetry).
+
+    For every mode k != 0 inside the cube |k_i| <= kcut_i (default
+    ceil(n_i / 4) - 1, the cutoff of a cubic product):
+        psihat = A(|k|) exp(i t),  A = sqrt(E(|k|) / (4 pi |k|^2)),
+    k the physical wavenumber, t uniform in [0, 2 pi) from the counter-based
+    generator (draw 0 of the given field id, keyed by the integer
+    wavenumbers); amplitudes scaled so that the fluctuation carries
+    (1 - condensate) of the particle number sum_k |psihat|^2 = number, and the
+    k = 0 mode (the condensate, real and positive) the rest."""
+    nx, ny, nz = shape
+    al = np.array([1.0, 1.0, 1.0]) if box is None else 2.0 * np.pi / np.asarray(box, float)
+    if kcut is None:
+        kc = tuple(-(-m // 4) - 1 for m in shape)
+    elif np.isscalar(kcut):
+        kc = (kcut,) * 3
+    else:
+        kc = tuple(kcut)
+    kz, ky, kx = np.meshgrid(np.arange(-kc[2], kc[2] + 1), np.arange(-kc[1], kc[1] + 1),
+                             np.arange(-kc[0], kc[0] + 1), indexing="ij")
+    kz, ky, kx = kz.ravel(), ky.ravel(), kx.ravel()
+    nz0 = (kx != 0) | (ky != 0) | (kz != 0)
+    kx, ky, kz = kx[nz0], ky[nz0], kz[nz0]
+    k2 = (al[0] * kx) ** 2 + (al[1] * ky) ** 2 + (al[2] * kz) ** 2
+    a2 = spectrum(np.sqrt(k2)) / (4.0 * np.pi * k2)
+    tot = float(np.sum(a2))
+    a2 = a2 * ((1.0 - condensate) * number / tot if tot > 0 else 0.0)
+    t = 2.0 * np.pi * uniform(seed, field, kx, ky, kz, 0)
+    out = np.zeros((nz, ny, nx), dtype)
+    out[np.mod(kz, nz), np.mod(ky, ny), np.mod(kx, nx)] = np.sqrt(a2) * np.exp(1j * t)
+    out[0, 0, 0] = np.sqrt(condensate * number)
+    return out
+
+
+def plane_wave(shape, k=(1, 0, 0), amp=1.0, dtype=np.complex128):
+    """psi = amp exp(i k . x) (integer wavenumber k), full spectrum [nz][ny][nx]."""
+    nx, ny, nz = shape
+    out = np.zeros((nz, ny, nx), dtype)
+    out[k[2] % nz, k[1] % ny, k[0] % nx] = amp
     return out
 
 
