@@ -60,18 +60,27 @@ typedef enum {
     PST_ERR_UNSUPPORTED = 6    /* option not implemented for this plan */
 } pst_status;
 
-typedef enum { PST_NS = 0, PST_MHD = 1, PST_BOUSSINESQ = 2 } pst_solver;
+/* GPE: the Gross-Pitaevskii equation of a complex wavefunction psi (eq. gpe),
+ *   d psi / dt = i alpha Lap psi - i beta |psi|^2 psi,
+ * on the whole spectrum (c2c transforms), its cubic product dealiased by the
+ * cube |k_i| <= K = ceil(n/4) - 1 (4K < n), the linear part taken exactly by
+ * the unitary integrating factor exp(-i alpha |k|^2 h / 2). */
+typedef enum { PST_NS = 0, PST_MHD = 1, PST_BOUSSINESQ = 2, PST_GPE = 3 } pst_solver;
 typedef enum { PST_FP32 = 0, PST_FP64 = 1 } pst_precision;
 /* Dealiasing of the nonlinear terms (2/3 rule, K = ceil(n/3) - 1):
  * CUBE keeps max(|kx|, |ky|, |kz|) <= K; SPHERE keeps |k|^2 <= K^2.  The state
  * always holds the cube; under SPHERE the modes between sphere and cube get
- * no nonlinear term (they evolve by the linear part alone).  Ensembles use the
- * cube. */
-typedef enum { PST_DEALIAS_CUBE = 0, PST_DEALIAS_SPHERE = 1 } pst_dealias;
+ * no nonlinear term (they evolve by the linear part alone).  NONE (tests
+ * only: it shows the aliasing the other two remove) uses K = n/2 - 1, i.e.
+ * keeps every mode except the Nyquist ones, so products alias.  Ensembles use
+ * the cube. */
+typedef enum { PST_DEALIAS_CUBE = 0, PST_DEALIAS_SPHERE = 1, PST_DEALIAS_NONE = 2 } pst_dealias;
 /* U: velocity (3 components); B: magnetic field (MHD, 3 components); THETA:
  * temperature fluctuation (Boussinesq, 1 component: physical [1][n][n][n],
- * spectral [1][n][n][n/2+1]). */
-typedef enum { PST_FIELD_U = 0, PST_FIELD_B = 1, PST_FIELD_THETA = 2 } pst_field;
+ * spectral [1][n][n][n/2+1]); PSI: the wavefunction (GPE, 1 complex
+ * component: physical complex [1][n][n][n], spectral complex [1][n][n][n], kx
+ * on the full axis like ky and kz). */
+typedef enum { PST_FIELD_U = 0, PST_FIELD_B = 1, PST_FIELD_THETA = 2, PST_FIELD_PSI = 3 } pst_field;
 typedef enum { PST_SPACE_PHYS = 0, PST_SPACE_SPEC = 1 } pst_space;
 typedef enum { PST_MEM_HOST = 0, PST_MEM_DEVICE = 1 } pst_mem;
 
@@ -91,12 +100,14 @@ typedef struct {
     int dealias;      /* pst_dealias */
     unsigned flags;   /* PST_FLAG_* */
     double nbv;       /* Brunt-Vaisala frequency N (Boussinesq; ignored otherwise) */
+    double alpha;     /* GPE: coefficient of the Laplacian (hbar / 2m); ignored otherwise */
+    double beta;      /* GPE: coupling of |psi|^2 psi (g / hbar); ignored otherwise */
 } pst_params;
 
 typedef struct {
     int n, kcut;              /* grid size and dealias cutoff K */
-    int ncomp;                /* state components: 3 (NS), 6 (MHD: u, b) or 4 (Boussinesq: u, theta) */
-    size_t modes_per_comp;    /* stored modes per component: (K+1)(2K+1)^2 */
+    int ncomp;                /* state components: 3 (NS), 6 (MHD: u, b), 4 (Boussinesq: u, theta), 1 (GPE) */
+    size_t modes_per_comp;    /* stored modes per component: (K+1)(2K+1)^2, GPE (2K+1)^3 */
     size_t workspace_bytes;   /* device bytes owned by the plan */
     int radices[4];           /* FFT radix schedule of the n-point transforms (0-terminated) */
     int tile_lines;           /* lines per workgroup in the strided passes */
@@ -161,7 +172,8 @@ pst_status pst_set_forcing(pst_plan *plan, const void *fhat, int mem);
 
 /* Nonlinear right-hand side of the state in state_dev (device, spectral
  * layout; NS: [3] comps of u, MHD: [6] = u then b, Boussinesq: [4] = u then
- * theta), written to rhs_dev (same layout):  NS  N = D P F[u x w] + f;  MHD
+ * theta, GPE: [1] psi on the full spectrum), written to rhs_dev (same layout);
+ * GPE: N = -i beta D F[|psi|^2 psi];  NS  N = D P F[u x w] + f;  MHD
  * N_u = D P F[u x w + j x b], N_b = D (i k x F[u x b]);  Boussinesq
  * N_u = D P (F[u x w] - N thetahat zhat) + f, N_theta = D (-F[u . grad theta]
  * + N w_z) (eq. mom, eq. temp; u . grad u in rotational form, its gradient
@@ -175,7 +187,10 @@ pst_status pst_step(pst_plan *plan, int nsteps);
 
 /* Energies E = 1/2 <|v|^2> = 1/2 sum_k w |vhat|^2 (w = 1 on kx = 0, else 2)
  * of u and of b (MHD) or theta (Boussinesq: 1/2 <theta^2>); out[1] = 0 for
- * NS.  Accumulated in double.  Synchronous.  NONFINITE if either is NaN/Inf. */
+ * NS.  GPE: out[0] = particle number sum_k |psihat|^2 = <|psi|^2>, out[1] =
+ * kinetic energy alpha sum_k |k|^2 |psihat|^2 (the interaction energy
+ * beta/2 <|psi|^4> needs psi at the grid points: pst_get_state PHYS).
+ * Accumulated in double.  Synchronous.  NONFINITE if either is NaN/Inf. */
 pst_status pst_energy(pst_plan *plan, double out[2]);
 
 /* Enstrophies Z = 1/2 sum_k w |k|^2 |vhat|^2 of u and of b or theta (out[1]
@@ -186,8 +201,9 @@ pst_status pst_energy(pst_plan *plan, double out[2]);
 pst_status pst_enstrophy(pst_plan *plan, double out[2]);
 
 /* Shell spectrum E(s) = 1/2 sum_{floor(|k|+1/2) = s} w |vhat|^2 for
- * s = 0..nshells-1 (double).  nshells must be >= floor(sqrt(3) K + 1/2) + 1.
- * Synchronous. */
+ * s = 0..nshells-1 (double; GPE: the number spectrum sum_shell |psihat|^2),
+ * summed in a fixed order (bitwise repeatable).
+ * nshells must be in [floor(sqrt(3) K + 1/2) + 1, 2048].  Synchronous. */
 pst_status pst_spectrum(pst_plan *plan, int field, double *Ek, int nshells);
 
 /* Standalone unpruned 3D transforms of nfields fields (device pointers, the
@@ -242,8 +258,15 @@ pst_status pst_ensemble_set_state(pst_ensemble *ens, int run, const void *uhat, 
 pst_status pst_ensemble_get_state(pst_ensemble *ens, int run, void *uhat, int mem);
 
 /* Advance every run by nsteps steps in the current mode; the persistent modes
- * synchronise the stream and return HIP if a device-wide barrier timed out. */
+ * synchronise the stream and return HIP if a device-wide barrier timed out in
+ * any of the nsteps steps (the states are then undefined).  Every barrier wait
+ * is bounded: after a timeout the remaining steps of the call return at once. */
 pst_status pst_ensemble_step(pst_ensemble *ens, int nsteps);
+/* Test only: polls of a device-wide barrier before it gives up and flags a
+ * timeout (default 4194304; 0 makes every barrier that is not already complete
+ * time out, so the error path can be exercised with every kernel exiting
+ * normally).  INVALID_ARG if polls < 0. */
+pst_status pst_ensemble_set_spin_limit(pst_ensemble *ens, long long polls);
 pst_status pst_ensemble_set_mode(pst_ensemble *ens, int mode);
 /* Current mode (PST_ENS_*), e.g. the one pst_ensemble_autotune picked. */
 pst_status pst_ensemble_get_mode(const pst_ensemble *ens, int *mode);

@@ -41,8 +41,14 @@ static const EnsKernels* ens_kernels(int v) {
     }
 }
 
-__global__ void k_ens_reset(unsigned* bar, int* err) {
+// Barrier words back to zero before every persistent step (a timed-out
+// barrier leaves its counters part-way).  The timeout flag is not touched
+// here: it is cleared by the host before and after each pst_ensemble_step, so
+// a timeout in any step of a multi-step call is still reported.
+__global__ void k_ens_reset_bar(unsigned* bar) {
     for (int i = threadIdx.x; i < ENS_BAR_WORDS; i += blockDim.x) bar[i] = 0u;
+}
+__global__ void k_ens_clear_err(int* err) {
     if (threadIdx.x == 0) err[0] = 0;
 }
 
@@ -233,6 +239,7 @@ struct pst_ensemble {
     hipGraph_t graph;
     hipGraphExec_t gexec;
     bool graph_valid;
+    long long spin_limit;         // polls of a device-wide barrier before it reports a timeout
     std::string msg;
     size_t owned;
 };
@@ -285,7 +292,7 @@ static EnsDesc<float> make_desc(pst_ensemble* E) {
     d.h = (float)E->p.dt;
     d.bar = E->bar;
     d.err = E->err;
-    d.spin_limit = 1ll << 22;
+    d.spin_limit = E->spin_limit;
     return d;
 }
 
@@ -309,7 +316,7 @@ static void launch_step(pst_ensemble* E) {
             E->desc_host = d;
             hipMemcpyAsync(E->desc_dev, &E->desc_host, sizeof d, hipMemcpyHostToDevice, E->stream);
         }
-        hipLaunchKernelGGL(k_ens_reset, dim3(1), dim3(64), 0, E->stream, E->bar, E->err);
+        hipLaunchKernelGGL(k_ens_reset_bar, dim3(1), dim3(64), 0, E->stream, E->bar);
         K->launch_persistent(E->desc_dev, E->grids[E->var], E->stream);
         return;
     }
@@ -398,6 +405,7 @@ extern "C" pst_status pst_ensemble_create(int nruns, const int* n, const pst_par
     E->nruns = nruns;
     E->mode = 0;
     E->graph_valid = false;
+    E->spin_limit = 1ll << 22;
     memset(&E->desc_host, 0xff, sizeof E->desc_host);
     int ci = 0;
     for (auto& kv : cls_of) {
@@ -461,7 +469,8 @@ extern "C" pst_status pst_ensemble_create(int nruns, const int* n, const pst_par
             return s;
         }
     }
-    hipLaunchKernelGGL(k_ens_reset, dim3(1), dim3(64), 0, E->stream, E->bar, E->err);
+    hipLaunchKernelGGL(k_ens_reset_bar, dim3(1), dim3(64), 0, E->stream, E->bar);
+    hipLaunchKernelGGL(k_ens_clear_err, dim3(1), dim3(64), 0, E->stream, E->err);
     E->var = 0;
     for (int v = 0; v < ENS_NVAR; ++v) E->grids[v] = persistent_grid(ens_kernels(v));
     if (hipStreamSynchronize(E->stream) != hipSuccess) {
@@ -511,12 +520,23 @@ extern "C" pst_status pst_ensemble_get_state(pst_ensemble* E, int run, void* uha
     return PST_OK;
 }
 
+// Read the timeout flag of the persistent steps enqueued since it was last
+// cleared, then clear it for the next call.
 static pst_status check_err_flag(pst_ensemble* E) {
     int err = 0;
     if (hipMemcpyAsync(&err, E->err, sizeof(int), hipMemcpyDeviceToHost, E->stream) != hipSuccess ||
         hipStreamSynchronize(E->stream) != hipSuccess)
         return efail(E, PST_ERR_HIP, "reading the barrier flag failed");
+    hipLaunchKernelGGL(k_ens_clear_err, dim3(1), dim3(64), 0, E->stream, E->err);
     if (err) return efail(E, PST_ERR_HIP, "persistent step: device-wide barrier timed out (grid not co-resident?)");
+    return PST_OK;
+}
+
+extern "C" pst_status pst_ensemble_set_spin_limit(pst_ensemble* E, long long polls) {
+    if (!E) return PST_ERR_INVALID_ARG;
+    if (polls < 0) return efail(E, PST_ERR_INVALID_ARG, "spin limit %lld < 0", polls);
+    drop_graph(E);   // a captured step holds the old descriptor upload
+    E->spin_limit = polls;
     return PST_OK;
 }
 
@@ -538,6 +558,10 @@ extern "C" pst_status pst_ensemble_step(pst_ensemble* E, int nsteps) {
     if (!E) return PST_ERR_INVALID_ARG;
     if (nsteps < 0) return efail(E, PST_ERR_INVALID_ARG, "nsteps < 0");
     if (nsteps == 0) return PST_OK;
+    // the timeout flag starts clear (outside any captured graph); every step of
+    // this call leaves it set if one of its barriers timed out, and the
+    // persistent kernel returns at once while it is set
+    if (E->mode <= 1) hipLaunchKernelGGL(k_ens_clear_err, dim3(1), dim3(64), 0, E->stream, E->err);
     if (E->mode == 0 || E->mode == 4) {  // one step's launches replayed from a captured graph
         if (!E->graph_valid) {
             hipStream_t cs = nullptr;

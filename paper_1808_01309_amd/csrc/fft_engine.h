@@ -160,16 +160,41 @@ __host__ __device__ constexpr int span_at(int s) {
 // LDS views.  A line view places one line contiguously with one pad slot
 // every 8 points (breaks the power-of-two bank strides of the stage writes);
 // a tile view interleaves TL lines, point p of the thread's line at p * TLP.
+//
+// at(base, delta) is operator()(base + delta) for the case where base + delta
+// carries nothing into bit 3 beyond what delta does: delta a multiple of 8, or
+// base % 8 + delta < 8.  The padded index then splits into a per-thread part
+// and a compile-time offset, so unrolled stages address LDS by immediates.
 template <typename T>
 struct LineLds {
     cx<T>* p;
     __device__ __forceinline__ cx<T>& operator()(int i) const { return p[i + (i >> 3)]; }
+    __device__ __forceinline__ cx<T>& at(int base, int delta) const {
+        return p[(base + (base >> 3)) + (delta + (delta >> 3))];
+    }
     static constexpr int size(int n) { return n + n / 8; }
 };
 template <typename T, int TLP>
 struct TileLds {
     cx<T>* p;  // already offset by the thread's line
     __device__ __forceinline__ cx<T>& operator()(int i) const { return p[i * TLP]; }
+    __device__ __forceinline__ cx<T>& at(int base, int delta) const { return p[(base + delta) * TLP]; }
+};
+// Block-padded tile view: point i of the TL interleaved lines at
+// (i + i / 8) TL, i.e. one empty group of TL slots after every 8 points.  The
+// accesses of a radix-8 Stockham stage (points g + r n/R of consecutive g, or
+// 8 g + r, or 64 (g / 8) + g % 8 + 8 r) then fall on distinct LDS banks for
+// tiles of 4 or 8 lines, where a one-slot pad per point (TileLds) gives
+// two-way conflicts; and i / 8 splits into a per-thread base plus a
+// compile-time offset for all of them, so no extra address arithmetic.
+template <typename T, int TL>
+struct TileBlk {
+    cx<T>* p;  // already offset by the thread's line
+    __device__ __forceinline__ cx<T>& operator()(int i) const { return p[(i + (i >> 3)) * TL]; }
+    __device__ __forceinline__ cx<T>& at(int base, int delta) const {
+        return p[(base + (base >> 3)) * TL + (delta + (delta >> 3)) * TL];
+    }
+    static constexpr int size(int n) { return (n + n / 8) * TL; }
 };
 
 // Synchronisation of the LDS exchanges between transform stages: the whole
@@ -244,18 +269,29 @@ struct Fft {
             const Lds lds = (PP && ((ex + s) & 1)) ? l1 : l0;
             constexpr int R2 = radix_at<P, REV>(s + 1);
             constexpr int NB2 = E / R2;
+            // writes base + r NS: carry-free when NS is a multiple of 8, or
+            // NS R = 8 (then base % 8 = b % NS and base % 8 + r NS < 8);
+            // reads g + i G + r N / R2: when G and N / R2 are multiples of 8
+            constexpr bool WOK = NS % 8 == 0 || NS * R == 8;
+            constexpr bool ROK = G % 8 == 0 && (N / R2) % 8 == 0;
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
                 const int b = g + i * G;
                 const int base = (b / NS) * NS * R + (b % NS);
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds(base + r * NS) = v[i * R + r];
+                for (int r = 0; r < R; ++r) {
+                    if constexpr (WOK) lds.at(base, r * NS) = v[i * R + r];
+                    else lds(base + r * NS) = v[i * R + r];
+                }
             }
             lds_sync<WS>();
 #pragma unroll
             for (int i = 0; i < NB2; ++i)
 #pragma unroll
-                for (int r = 0; r < R2; ++r) v[i * R2 + r] = lds(g + i * G + r * (N / R2));
+                for (int r = 0; r < R2; ++r) {
+                    if constexpr (ROK) v[i * R2 + r] = lds.at(g, i * G + r * (N / R2));
+                    else v[i * R2 + r] = lds(g + i * G + r * (N / R2));
+                }
             if constexpr (!PP) lds_sync<WS>();
             stage<s + 1, PP>(v, g, l0, l1, ex, tw);
         }

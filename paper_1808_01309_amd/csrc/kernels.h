@@ -14,6 +14,8 @@
 // Only modes inside the dealiasing cube are ever read or written, so the
 // transforms are pruned on both ends; physical-space fields never touch HBM.
 #pragma once
+#include <type_traits>
+
 #include "fft_engine.h"
 #include "plan.h"
 
@@ -121,6 +123,11 @@ struct RkArgs {
     int kf;
     int lin_only;
     int sph2;          // spherical truncation: nonlinear terms kept for |k|^2 <= sph2; -1: the cube
+    // Gross-Pitaevskii: unitary factors exp(-i alpha |k|^2 h / 2), exp(-i alpha |k|^2 h)
+    // by |k|^2, and the coupling beta of the cubic term
+    const cx<T>* Ec;
+    const cx<T>* E2c;
+    T beta;
 };
 
 // ------------------------------------------------------------ zinv + curl
@@ -281,7 +288,7 @@ __global__ __launch_bounds__((CF::G * CF::TL)) void k_ypass(const cx<T>* __restr
 // price of one), cross products in registers, forward x of the products
 // packed two per complex line, split by Hermitian symmetry, kx <= K kept.
 // SYS: 0 Navier-Stokes, 1 MHD, 2 Boussinesq (nbv: Brunt-Vaisala frequency).
-template <typename T, class CF, int NT, int SYS, bool PPB = false>
+template <typename T, class CF, int NT, int SYS, bool PPB = false, bool BLK = false>
 __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
                                            const cx<T>* __restrict__ tw, const Geo& geo, int64_t unit, int tid,
                                            cx<T>* sm, T nbv = T(0)) {
@@ -303,10 +310,17 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     const bool zin = valid && z < N;
     // PPB: two LDS buffers of the block's tiles, used by alternate phases
     // (staging of a pair, transform exchanges, output staging), so that each
-    // phase needs a single barrier (see Fft::run_pp).
-    constexpr int TSZ = SG * N * TLP;
-    const TileLds<T, TLP> lds{sm + s * N * TLP + t};
-    const TileLds<T, TLP> lds1{sm + (PPB ? TSZ : 0) + s * N * TLP + t};
+    // phase needs a single barrier (see Fft::run_pp).  BLK: block-padded tile
+    // layout (TileBlk) instead of one pad slot per point.
+    using TV = std::conditional_t<BLK, TileBlk<T, TL>, TileLds<T, TLP>>;
+    constexpr int TSZ1 = BLK ? TileBlk<T, TL>::size(N) : N * TLP;   // elements of one tile
+    constexpr int TSZ = SG * TSZ1;
+    // LDS indices of the staging and output phases split into a per-thread
+    // base and multiples of 8 (see LineLds::at) when G and the first / last
+    // stage spans N / R are multiples of 8
+    constexpr bool SPLIT = G % 8 == 0 && N % (8 * FI::R_FIRST) == 0 && N % (8 * FF::R_LAST) == 0;
+    const TV lds{sm + s * TSZ1 + t};
+    const TV lds1{sm + (PPB ? TSZ : 0) + s * TSZ1 + t};
     int ex = 0;   // LDS phases so far
     const int64_t nn = (int64_t)N * N;
     const int64_t off = (int64_t)y * N + z;
@@ -315,27 +329,61 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     // LDS (coalesced along z); the packed line Z = V + i W and its Hermitian
     // mirror Z(N - kx) = conj V + i conj W are then assembled from LDS.
     cx<T> v[NP][E];
-#pragma unroll
-    for (int pi = 0; pi < NP; ++pi) {
-        // this tile's LDS (2 (K+1) TLP <= N TLP)
-        cx<T>* const stage = sm + ((PPB && (ex & 1)) ? TSZ : 0) + s * N * TLP;
+    // A thread's kept rows of a pair are kx = g + i G (i < IT, kx <= K < N/2).
+    // All of them are loaded at once (a fixed, predicated count, so the loads
+    // are in flight together), and the next pair's loads are issued before the
+    // current pair's LDS barrier and assembly, which hides their latency.
+    constexpr int IT = (N / 2 - 1) / G + 1;
+    cx<T> la[IT], lb[IT];
+    auto load_pair = [&](int pi) {
         // pairs (v_c, (i k x v)_c); Boussinesq adds (theta_x, theta_y), (theta_z, theta)
         const int fu = (BQ && pi >= 3) ? 6 + 2 * (pi - 3) : (pi / 3) * 6 + pi % 3;
         const int fw = (BQ && pi >= 3) ? fu + 1 : fu + 3;
-        for (int kx = g; kx <= K; kx += G) {
-            stage[kx * TLP + t] = zin ? Bf[fu * geo.sb + kx * nn + off] : czero<T>();
-            stage[(K + 1 + kx) * TLP + t] = zin ? Bf[fw * geo.sb + kx * nn + off] : czero<T>();
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int kx = g + i * G;
+            const bool ok = zin && kx <= K;
+            la[i] = ok ? Bf[fu * geo.sb + kx * nn + off] : czero<T>();
+            lb[i] = ok ? Bf[fw * geo.sb + kx * nn + off] : czero<T>();
         }
+    };
+    load_pair(0);
+#pragma unroll
+    for (int pi = 0; pi < NP; ++pi) {
+        // this tile's LDS, points 0 .. 2K+1 < N of the tile view
+        const TV stage{sm + ((PPB && (ex & 1)) ? TSZ : 0) + s * TSZ1 + t};
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int kx = g + i * G;
+            if (kx <= K) {
+                if constexpr (SPLIT) {
+                    stage.at(g, i * G) = la[i];
+                    stage.at(K + 1 + g, i * G) = lb[i];
+                } else {
+                    stage(kx) = la[i];
+                    stage(K + 1 + kx) = lb[i];
+                }
+            }
+        }
+        if (pi + 1 < NP) load_pair(pi + 1);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int p = FI::first_pos(g, e);
             const bool lo = p <= K, hi = p >= N - K;
-            const int kk = lo ? p : N - p;
+            // SPLIT: p = g + d with d = first_pos(0, e) a multiple of 8, so
+            // kk = g + d or N - g - d splits as at() needs
+            const int d = FI::first_pos(0, e), kk = lo ? p : N - p;
             cx<T> Z = czero<T>();
             if (lo || hi) {
-                const cx<T> U = stage[kk * TLP + t];
-                const cx<T> W = stage[(K + 1 + kk) * TLP + t];
+                cx<T> U, W;
+                if constexpr (SPLIT) {
+                    U = lo ? stage.at(g, d) : stage.at(N - g, -d);
+                    W = lo ? stage.at(K + 1 + g, d) : stage.at(K + 1 + N - g, -d);
+                } else {
+                    U = stage(kk);
+                    W = stage(K + 1 + kk);
+                }
                 if (p == 0) Z = {U.x, W.x};
                 else if (lo) Z = {U.x - W.y, U.y + W.x};
                 else Z = {U.x + W.y, W.x - U.y};
@@ -389,14 +437,24 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
         } else {
             FF::run(v[po], g, lds, tw);
         }
-        const TileLds<T, TLP> lo = (PPB && (ex & 1)) ? lds1 : lds;
+        const TV lo = (PPB && (ex & 1)) ? lds1 : lds;
 #pragma unroll
-        for (int e = 0; e < E; ++e) lo(FF::last_pos(g, e)) = v[po][e];
+        for (int e = 0; e < E; ++e) {
+            if constexpr (SPLIT) lo.at(g, FF::last_pos(0, e)) = v[po][e];
+            else lo(FF::last_pos(g, e)) = v[po][e];
+        }
         __syncthreads();
         if (zin) {
             const int fa = 2 * po, fb = 2 * po + 1;
-            for (int kx = g; kx <= K; kx += G) {
-                const cx<T> a = lo(kx), b = lo(kx == 0 ? 0 : N - kx);
+            for (int kx = g, d = 0; kx <= K; kx += G, d += G) {
+                cx<T> a, b;
+                if constexpr (SPLIT) {
+                    a = lo.at(g, d);
+                    b = kx == 0 ? lo(0) : lo.at(N - g, -d);
+                } else {
+                    a = lo(kx);
+                    b = lo(kx == 0 ? 0 : N - kx);
+                }
                 const cx<T> A = {T(0.5) * (a.x + b.x), T(0.5) * (a.y - b.y)};
                 Cf[fa * geo.sb + kx * nn + off] = A;
                 if (fb < NOUT) {
@@ -412,8 +470,13 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
 
 // Two tile buffers for Navier-Stokes where they fit in the 160 KB of LDS of
 // a CU (for MHD the alternating views cost registers, and occupancy at 1024).
+// LDS elements of one buffer of the x pass (block-padded tiles).
+template <typename T, class CF, int NT> constexpr int xtile_lds() {
+    return (NT / (CF::G * CF::TL)) * TileBlk<T, CF::TL>::size(CF::N);
+}
+
 template <typename T, class CF, bool MHD> constexpr bool xpass_pp() {
-    return !MHD && 2 * tile_lds<T, CF, CF::G * CF::TL>() * (int)sizeof(cx<T>) <= 160 * 1024;
+    return !MHD && 2 * xtile_lds<T, CF, CF::G * CF::TL>() * (int)sizeof(cx<T>) <= 160 * 1024;
 }
 
 // Two workgroups per CU for the FP32 Navier-Stokes x pass below n = 1024: its
@@ -440,18 +503,18 @@ __global__ __launch_bounds__((CF::G * CF::TL), (xpass_two_per_cu<T, CF::N, SYS>(
                                                           const cx<T>* __restrict__ tw, Geo geo, T nbv) {
     constexpr bool PPB = xpass_pp<T, CF, SYS == 1>();
     constexpr int PER = xpass_per<T, CF, SYS>();
-    __shared__ cx<T> sm[(PPB ? 2 : 1) * tile_lds<T, CF, CF::G * CF::TL>()];
+    __shared__ cx<T> sm[(PPB ? 2 : 1) * xtile_lds<T, CF, CF::G * CF::TL>()];
     // each XCD takes a contiguous range of tiles (measured faster, most for the
     // narrow MHD tiles at n = 1024 whose rows share cache lines)
     if constexpr (PER == 1) {
-        xpass_body<T, CF, CF::G * CF::TL, SYS, PPB>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm, nbv);
+        xpass_body<T, CF, CF::G * CF::TL, SYS, PPB, true>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm, nbv);
     } else {
         const int64_t ntl = (int64_t)CF::N * ztiles<CF::N, CF::TL>();
         const int64_t u0 = xcd_unit() * PER;
         const int64_t u1 = u0 + PER < ntl ? u0 + PER : ntl;
         for (int64_t u = u0; u < u1; ++u) {
             if (u > u0) __syncthreads();   // the previous tile's last LDS reads
-            xpass_body<T, CF, CF::G * CF::TL, SYS, PPB>(Bf, Cf, tw, geo, u, threadIdx.x, sm, nbv);
+            xpass_body<T, CF, CF::G * CF::TL, SYS, PPB, true>(Bf, Cf, tw, geo, u, threadIdx.x, sm, nbv);
         }
     }
 }
@@ -831,6 +894,211 @@ __global__ __launch_bounds__(NCfg<N>::G * tile_lines<T>()) void k_fft_cols_m(
     }
 }
 
+// ------------------------------------------------------------ Gross-Pitaevskii
+// The wavefunction psi of eq. gpe is complex: its coefficients fill the whole
+// spectrum and every axis is a full c2c axis.  The compact state is
+// [jx][jy][jz] over the kept cube |k_i| <= K (K = ceil(n/4) - 1: 4K < n, no
+// aliasing of the cubic product); geo.nxk = M.  One right-hand side is
+//   zinv   state (kept kz)     -> backward z                        -> A
+//   yinv   (ypass_body, 1 field)                                    -> B
+//   xpass  B (kept kx rows)    -> backward x, |psi|^2 psi, forward x,
+//                                 keep kept kx                        -> C
+//   yfwd   (ypass_body, 1 field)                                    -> D
+//   zfwd   D                   -> forward z, keep kept kz, -i beta / n^3,
+//                                 Lawson RK stage with exp(-i alpha |k|^2 h / 2)
+
+template <typename T, class CF, int NT>
+__device__ __forceinline__ void zinv_gpe_body(const cx<T>* __restrict__ st, cx<T>* __restrict__ A,
+                                              const cx<T>* __restrict__ tw, const Geo& geo, int64_t unit, int tid,
+                                              cx<T>* sm) {
+    constexpr int N = CF::N, G = CF::G;
+    using F = Fft<T, typename CF::P, G, true, false, sizeof(T) == 8 && G <= 64, sizeof(T) == 4>;
+    constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
+    const int l = tid / G, g = tid % G;
+    const int64_t line = unit * LPB + l;
+    const bool active = line < (int64_t)geo.nxk * geo.M;
+    const LineLds<T> lds{sm + l * LS};
+    const cx<T>* src = st + (active ? line : 0) * geo.M;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = j_of_pos(F::first_pos(g, e), geo);
+        v[e] = (active && j >= 0) ? src[j] : czero<T>();
+    }
+    F::run(v, g, lds, tw);
+    if (active) {
+        cx<T>* dst = A + line * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) dst[F::last_pos(g, e)] = v[e];
+    }
+}
+
+template <typename T, class CF>
+__global__ __launch_bounds__(LINE_BLOCK) void k_zinv_gpe(const cx<T>* __restrict__ st, cx<T>* __restrict__ A,
+                                                          const cx<T>* __restrict__ tw, Geo geo) {
+    __shared__ cx<T> sm[line_lds<T, CF, LINE_BLOCK>()];
+    zinv_gpe_body<T, CF, LINE_BLOCK>(st, A, tw, geo, blockIdx.x, threadIdx.x, sm);
+}
+
+// Tile of TL consecutive z at one y: the kept kx rows of psi (read straight
+// from HBM, TL consecutive z per row), backward x, the cubic product
+// |psi|^2 psi at each point, forward x, kept rows written back.
+template <typename T, class CF, int NT>
+__device__ __forceinline__ void xpass_gpe_body(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
+                                               const cx<T>* __restrict__ tw, const Geo& geo, int64_t unit, int tid,
+                                               cx<T>* sm) {
+    constexpr int N = CF::N, G = CF::G, TL = CF::TL, TT = G * TL, SG = NT / TT;
+    using FI = Fft<T, typename CF::P, G, true, false, false, sizeof(T) == 4>;
+    using FF = Fft<T, typename CF::P, G, false, true, false, sizeof(T) == 4>;
+    constexpr int E = FI::E, NTZ = ztiles<N, TL>();
+    const int s = tid / TT, r = tid % TT;
+    const int t = r % TL, g = r / TL;
+    const int64_t tile = unit * SG + s;
+    const bool valid = tile < (int64_t)N * NTZ;
+    const int zt = valid ? (int)(tile % NTZ) : 0;
+    const int y = valid ? (int)(tile / NTZ) : 0;
+    const int z = zt * TL + t;
+    const bool zin = valid && z < N;
+    const TileBlk<T, TL> lds{sm + s * TileBlk<T, TL>::size(N) + t};
+    const int64_t nn = (int64_t)N * N, off = (int64_t)y * N + z;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = j_of_pos(FI::first_pos(g, e), geo);
+        v[e] = (zin && j >= 0) ? Bf[j * nn + off] : czero<T>();
+    }
+    FI::run(v, g, lds, tw);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const T a2 = v[e].x * v[e].x + v[e].y * v[e].y;
+        v[e] = {a2 * v[e].x, a2 * v[e].y};
+    }
+    FF::run(v, g, lds, tw);
+    if (zin) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = j_of_pos(FF::last_pos(g, e), geo);
+            if (j >= 0) Cf[j * nn + off] = v[e];
+        }
+    }
+}
+
+template <typename T, class CF>
+__global__ __launch_bounds__((CF::G * CF::TL)) void k_xpass_gpe(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
+                                                               const cx<T>* __restrict__ tw, Geo geo) {
+    __shared__ cx<T> sm[xtile_lds<T, CF, CF::G * CF::TL>()];
+    xpass_gpe_body<T, CF, CF::G * CF::TL>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm);
+}
+
+// Lawson RK stage update with complex integrating factors (the arithmetic of
+// rk_apply with E, E2 complex).
+template <typename T>
+__device__ __forceinline__ void rk_apply_cx(int mode, cx<T>* __restrict__ U, cx<T>* __restrict__ V,
+                                            cx<T>* __restrict__ Acc, cx<T>* __restrict__ R, T h, int64_t idx, cx<T> E,
+                                            cx<T> E2, cx<T> nk) {
+    if (mode == Z_RHS) {
+        R[idx] = nk;
+        return;
+    }
+    switch (mode) {
+        case Z_RK4_0: {
+            const cx<T> un = U[idx];
+            V[idx] = cmul(E, cadd(un, cscale(nk, T(0.5) * h)));
+            Acc[idx] = cmul(E2, cadd(un, cscale(nk, h / T(6))));
+        } break;
+        case Z_RK4_1: {
+            const cx<T> un = U[idx], ac = Acc[idx], en = cmul(E, nk);
+            V[idx] = cadd(cmul(E, un), cscale(nk, T(0.5) * h));
+            Acc[idx] = cadd(ac, cscale(en, h / T(3)));
+        } break;
+        case Z_RK4_2: {
+            const cx<T> un = U[idx], ac = Acc[idx], en = cmul(E, nk);
+            V[idx] = cadd(cmul(E2, un), cscale(en, h));
+            Acc[idx] = cadd(ac, cscale(en, h / T(3)));
+        } break;
+        case Z_RK4_3: {
+            const cx<T> ac = Acc[idx];
+            U[idx] = cadd(ac, cscale(nk, h / T(6)));
+        } break;
+        case Z_RK2_0: {
+            const cx<T> un = U[idx];
+            V[idx] = cmul(E2, cadd(un, cscale(nk, h)));
+            Acc[idx] = cmul(E2, cadd(un, cscale(nk, T(0.5) * h)));
+        } break;
+        case Z_RK2_1: {
+            const cx<T> ac = Acc[idx];
+            U[idx] = cadd(ac, cscale(nk, T(0.5) * h));
+        } break;
+        default: break;
+    }
+}
+
+template <typename T, class CF, int NT>
+__device__ __forceinline__ void zfwd_gpe_lines(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw,
+                                               const Geo& geo, const RkArgs<T>& ra, cx<T>* __restrict__ U,
+                                               cx<T>* __restrict__ V, cx<T>* __restrict__ Acc, cx<T>* __restrict__ R,
+                                               int mode, int64_t unit, int tid, cx<T>* sm) {
+    constexpr int N = CF::N, G = CF::G;
+    using F = Fft<T, typename CF::P, G, false, false, false, sizeof(T) == 4>;
+    constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
+    const int l = tid / G, g = tid % G;
+    const int64_t line = unit * LPB + l;
+    const bool active = line < (int64_t)geo.nxk * geo.M;
+    const int jx = active ? (int)(line / geo.M) : 0;
+    const int jy = active ? (int)(line % geo.M) : 0;
+    const int ikx = k_of_j(jx, geo), iky = k_of_j(jy, geo);
+    const LineLds<T> lds{sm + l * LS};
+    cx<T> v[E];
+    const cx<T>* src = D + (active ? line : 0) * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = active ? src[F::first_pos(g, e)] : czero<T>();
+    F::run(v, g, lds, tw);
+    if (!active) return;
+    // -i beta F[|psi|^2 psi] with the forward scale 1/n^3
+    const T sb = ra.beta / (T(N) * T(N) * T(N));
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int q = F::last_pos(g, e);
+        const int j = j_of_pos(q, geo);
+        if (j < 0) continue;
+        const int ikz = k_of_pos(q, N);
+        const int k2 = ikx * ikx + iky * iky + ikz * ikz;
+        cx<T> nk = {sb * v[e].y, -sb * v[e].x};
+        if (ra.lin_only) nk = czero<T>();
+        rk_apply_cx(mode, U, V, Acc, R, ra.h, line * geo.M + j, ra.Ec[k2], ra.E2c[k2], nk);
+    }
+}
+
+template <typename T, class CF>
+__global__ __launch_bounds__(LINE_BLOCK) void k_zfwd_gpe(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw,
+                                                          Geo geo, RkArgs<T> ra, int mode) {
+    __shared__ cx<T> sm[line_lds<T, CF, LINE_BLOCK>()];
+    zfwd_gpe_lines<T, CF, LINE_BLOCK>(D, tw, geo, ra, ra.U, ra.V, ra.Acc, ra.R, mode, blockIdx.x, threadIdx.x, sm);
+}
+
+// Contiguous complex lines of N points, one line per G threads: the x pass of
+// the standalone c2c transforms (in == out allowed).
+template <typename T, int N, bool INV>
+__global__ __launch_bounds__(LINE_BLOCK) void k_fft_lines(const cx<T>* in, cx<T>* out, const cx<T>* __restrict__ tw,
+                                                          int64_t nlines, T scale) {
+    using C = NCfg<N>;
+    using F = Fft<T, typename C::P, C::G, INV, false, false, sizeof(T) == 4>;
+    constexpr int G = C::G, E = F::E, LPB = LINE_BLOCK / G, LS = LineLds<T>::size(N);
+    __shared__ cx<T> sm[LPB * LS];
+    const int l = threadIdx.x / G, g = threadIdx.x % G;
+    const int64_t line = (int64_t)blockIdx.x * LPB + l;
+    const bool active = line < nlines;
+    const cx<T>* a = in + (active ? line : 0) * N;
+    cx<T> v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = active ? a[F::first_pos(g, e)] : czero<T>();
+    F::run(v, g, LineLds<T>{sm + l * LS}, tw);
+    if (!active) return;
+    cx<T>* o = out + line * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) o[F::last_pos(g, e)] = cscale(v[e], scale);
+}
+
 // ------------------------------------------------------------ launchers
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
@@ -847,7 +1115,10 @@ struct Impl {
         KTimer tm(P, PST_K_ZINV);
         const Geo& g = P->geo;
         const unsigned nb = (unsigned)line_units<LC, LINE_BLOCK>(g);
-        if (P->p.solver == PST_MHD)
+        if (P->p.solver == PST_GPE)
+            hipLaunchKernelGGL((k_zinv_gpe<T, LC>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
+                               (cx<T>*)P->A, (const cx<T>*)P->tw, g);
+        else if (P->p.solver == PST_MHD)
             hipLaunchKernelGGL((k_zinv<T, LC, 2, false>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
                                (cx<T>*)P->A, (const cx<T>*)P->tw, g);
         else if (P->p.solver == PST_BOUSSINESQ)
@@ -867,7 +1138,10 @@ struct Impl {
     static void xpass(pst_plan* P) {
         KTimer tm(P, PST_K_XPASS);
         const Geo& g = P->geo;
-        if (P->p.solver == PST_MHD) {
+        if (P->p.solver == PST_GPE) {
+            hipLaunchKernelGGL((k_xpass_gpe<T, TC>), dim3((unsigned)xtile_units<TC, TB>()), dim3(TB), 0, P->stream,
+                               (const cx<T>*)P->B, (cx<T>*)P->C, (const cx<T>*)P->tw, g);
+        } else if (P->p.solver == PST_MHD) {
             using XC = XCfg<T, N, true>;
             hipLaunchKernelGGL((k_xpass<T, XC, 1>), dim3((unsigned)xtile_units<XC, XC::G * XC::TL>()),
                                dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
@@ -911,8 +1185,14 @@ struct Impl {
         ra.kf = P->kf;
         ra.lin_only = (P->p.flags & PST_FLAG_LINEAR_ONLY) ? 1 : 0;
         ra.sph2 = P->p.dealias == PST_DEALIAS_SPHERE ? g.K * g.K : -1;
+        ra.Ec = (const cx<T>*)P->Etab[0];
+        ra.E2c = (const cx<T>*)P->E2tab[0];
+        ra.beta = (T)P->p.beta;
         const unsigned nb = (unsigned)line_units<LC, LINE_BLOCK>(g);
-        if (P->p.solver == PST_MHD)
+        if (P->p.solver == PST_GPE)
+            hipLaunchKernelGGL((k_zfwd_gpe<T, LC>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+                               (const cx<T>*)P->tw, g, ra, mode);
+        else if (P->p.solver == PST_MHD)
             hipLaunchKernelGGL((k_zfwd<T, LC, 1>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
                                (const cx<T>*)P->tw, g, ra, mode);
         else if (P->p.solver == PST_BOUSSINESQ)
@@ -961,6 +1241,43 @@ struct Impl {
             KTimer tm(P, PST_K_FFTX);
             hipLaunchKernelGGL((k_fftx_c2r<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
                                P->stream, (const cx<T>*)tmp, (T*)out, (const cx<T>*)P->tw, npairs);
+        }
+    }
+
+    static void fft_c2c(pst_plan* P, const void* in, void* out, int nf, int inverse) {
+        const int64_t plane = (int64_t)N * N;
+        const T s = inverse ? T(1) : T(1) / (T(N) * T(N) * T(N));
+        {
+            KTimer tm(P, PST_K_FFTX);
+            const int64_t nl = (int64_t)nf * plane;
+            if (inverse)
+                hipLaunchKernelGGL((k_fft_lines<T, N, true>), dim3(cdiv(nl, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                                   P->stream, (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)P->tw, nl, T(1));
+            else
+                hipLaunchKernelGGL((k_fft_lines<T, N, false>), dim3(cdiv(nl, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                                   P->stream, (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)P->tw, nl, T(1));
+        }
+        {
+            KTimer tm(P, PST_K_FFTY);
+            if (inverse)
+                hipLaunchKernelGGL((k_fft_strided<T, N, true>), dim3(cdiv(N, TL), (unsigned)(nf * N)), dim3(TB), 0,
+                                   P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, (int64_t)N,
+                                   (int64_t)N, plane, T(1));
+            else
+                hipLaunchKernelGGL((k_fft_strided<T, N, false>), dim3(cdiv(N, TL), (unsigned)(nf * N)), dim3(TB), 0,
+                                   P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, (int64_t)N,
+                                   (int64_t)N, plane, T(1));
+        }
+        {
+            KTimer tm(P, PST_K_FFTZ);
+            if (inverse)
+                hipLaunchKernelGGL((k_fft_strided<T, N, true>), dim3(cdiv(plane, TL), (unsigned)nf), dim3(TB), 0,
+                                   P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, plane, plane,
+                                   (int64_t)N * plane, s);
+            else
+                hipLaunchKernelGGL((k_fft_strided<T, N, false>), dim3(cdiv(plane, TL), (unsigned)nf), dim3(TB), 0,
+                                   P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, plane, plane,
+                                   (int64_t)N * plane, s);
         }
     }
 
@@ -1033,6 +1350,7 @@ struct Impl {
             l.zfwd = &zfwd;
             l.fft_r2c = &fft_r2c;
             l.fft_c2r = &fft_c2r;
+            l.fft_c2c = &fft_c2c;
             l.fft_r2c_modes = &fft_r2c_modes;
             l.fft_c2r_modes = &fft_c2r_modes;
             l.modes_yz_fwd = &modes_yz_fwd;

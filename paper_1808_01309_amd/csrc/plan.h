@@ -19,9 +19,12 @@ namespace pst {
 //   state   [ncomp][nxk][M][M]   (kx, jy, jz)       component stride sc
 //   A, D    [nf][nxk][M][n]      (kx, jy, z)        field stride sa
 //   B, C    [nf][nxk][n][n]      (kx, y, z)         field stride sb
+//   full = 1 (Gross-Pitaevskii): kx runs over the whole axis like ky and kz
+//   (compact index jx in [0, M), nxk = M); full = 0: kx = jx in [0, K].
 struct Geo {
     int n, K, M, nxk;
     int64_t sc, sa, sb;
+    int full;
 };
 
 __host__ __device__ inline int pos_of_j(int j, const Geo& g) { return j <= g.K ? j : j + g.n - g.M; }
@@ -97,6 +100,9 @@ struct Launchers {
     void (*zfwd)(pst_plan*, int mode, void* rhs_out);
     void (*fft_r2c)(pst_plan*, const void* in, void* out, int nf);
     void (*fft_c2r)(pst_plan*, const void* in, void* out, int nf, void* tmp);
+    // complex 3D transform [nf][n][n][n] (x fastest), forward (sign -, 1/n^3) or
+    // inverse (sign +, unscaled); in == out allowed
+    void (*fft_c2c)(pst_plan*, const void* in, void* out, int nf, int inverse);
     // transforms restricted to the retained-mode box (kx < m, ky, kz in [0, m) U [n-m, n)),
     // compact spectra [nf][2m][2m][m]; workspace nf n n m + nf n 2m m complex
     void (*fft_r2c_modes)(pst_plan*, const void* in, void* out, int nf, int m, void* tmp);

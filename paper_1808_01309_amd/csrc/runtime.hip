@@ -125,16 +125,22 @@ static void drain_timers(pst_plan* P) {
 template <typename T>
 __global__ void k_gather(const cx<T>* __restrict__ abi, cx<T>* __restrict__ st, Geo g, int ncomp) {
     const int64_t total = (int64_t)ncomp * g.sc;
-    const int nxh = g.n / 2 + 1;
+    const int nxh = g.full ? g.n : g.n / 2 + 1;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(i / g.sc);
         int64_t r = i % g.sc;
         const int jz = (int)(r % g.M);
         r /= g.M;
         const int jy = (int)(r % g.M);
-        const int kx = (int)(r / g.M);
+        const int jx = (int)(r / g.M);
         const int ky = k_of_j(jy, g), kz = k_of_j(jz, g);
         const int iy = (ky + g.n) % g.n, iz = (kz + g.n) % g.n;
+        if (g.full) {   // whole spectrum, no symmetry: a plain copy of the kept modes
+            const int ix = (k_of_j(jx, g) + g.n) % g.n;
+            st[i] = abi[(int64_t)c * g.n * g.n * g.n + ((int64_t)iz * g.n + iy) * g.n + ix];
+            continue;
+        }
+        const int kx = jx;
         const cx<T>* a = abi + (int64_t)c * g.n * g.n * nxh;
         cx<T> v = a[((int64_t)iz * g.n + iy) * nxh + kx];
         if (kx == 0) {
@@ -147,19 +153,22 @@ __global__ void k_gather(const cx<T>* __restrict__ abi, cx<T>* __restrict__ st, 
 
 template <typename T>
 __global__ void k_scatter(const cx<T>* __restrict__ st, cx<T>* __restrict__ abi, Geo g, int ncomp) {
-    const int nxh = g.n / 2 + 1;
+    const int nxh = g.full ? g.n : g.n / 2 + 1;
     const int64_t per = (int64_t)g.n * g.n * nxh, total = (int64_t)ncomp * per;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(i / per);
         int64_t r = i % per;
-        const int kx = (int)(r % nxh);
+        const int ix = (int)(r % nxh);
         r /= nxh;
         const int iy = (int)(r % g.n), iz = (int)(r / g.n);
         const int ky = k_of_pos(iy, g.n), kz = k_of_pos(iz, g.n);
+        // full axis: signed kx, compact jx as for ky and kz
+        const int kx = g.full ? k_of_pos(ix, g.n) : ix;
+        const int jx = g.full ? (kx >= 0 ? kx : kx + g.M) : kx;
         cx<T> v = {T(0), T(0)};
-        if (kx <= g.K && ky <= g.K && -ky <= g.K && kz <= g.K && -kz <= g.K) {
+        if (kx <= g.K && -kx <= g.K && ky <= g.K && -ky <= g.K && kz <= g.K && -kz <= g.K) {
             const int jy = ky >= 0 ? ky : ky + g.M, jz = kz >= 0 ? kz : kz + g.M;
-            v = st[(int64_t)c * g.sc + ((int64_t)kx * g.M + jy) * g.M + jz];
+            v = st[(int64_t)c * g.sc + ((int64_t)jx * g.M + jy) * g.M + jz];
         }
         abi[i] = v;
     }
@@ -176,8 +185,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_energy_part(const cx<T>* __rest
     double acc = 0.0;
     const int64_t per = g.sc;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (int64_t)gridDim.x * blockDim.x) {
-        const int kx = (int)(i / ((int64_t)g.M * g.M));
-        double w = kx == 0 ? 1.0 : 2.0;
+        const int jx = (int)(i / ((int64_t)g.M * g.M));
+        // half spectrum: weight 2 off the kx = 0 plane; the full spectrum counts each mode once
+        const int kx = g.full ? k_of_j(jx, g) : jx;
+        double w = (g.full || kx == 0) ? 1.0 : 2.0;
         if (k2w) {  // enstrophy: weight |k|^2
             const int ky = k_of_j((int)((i / g.M) % g.M), g), kz = k_of_j((int)(i % g.M), g);
             w *= (double)(kx * kx + ky * ky + kz * kz);
@@ -214,31 +225,53 @@ __global__ __launch_bounds__(RED_THREADS) void k_sum_final(const double* __restr
 
 constexpr int MAX_SHELLS = 2048;
 
+__device__ __forceinline__ int shell_of(long k2) { return (int)floor(sqrt((double)k2) + 0.5); }
+
+// Shell spectrum with a fixed summation order (bitwise repeatable): block s
+// owns shell s.  Its threads stride over the (kx, ky) lines; along a line the
+// shell index grows with |kz|, so the line's modes in shell s are the |kz| of
+// one contiguous range, found from an estimate and the exact test
+// floor(|k| + 1/2) = s.  Per-thread sums are then combined by a fixed tree.
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_spectrum(const cx<T>* __restrict__ st, Geo g, int c0, int nc,
-                                                          double* __restrict__ bins, int nshells) {
-    __shared__ double sh[MAX_SHELLS];
-    for (int i = threadIdx.x; i < nshells; i += RED_THREADS) sh[i] = 0.0;
-    __syncthreads();
-    const int64_t per = g.sc;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (int64_t)gridDim.x * blockDim.x) {
-        const int jz = (int)(i % g.M);
-        const int jy = (int)((i / g.M) % g.M);
-        const int kx = (int)(i / ((int64_t)g.M * g.M));
-        const int ky = k_of_j(jy, g), kz = k_of_j(jz, g);
-        const long k2 = (long)kx * kx + (long)ky * ky + (long)kz * kz;
-        const int s = (int)floor(sqrt((double)k2) + 0.5);
-        if (s >= nshells) continue;
-        double a = 0.0;
-        for (int c = 0; c < nc; ++c) {
-            const cx<T> v = st[(int64_t)(c0 + c) * per + i];
-            a += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+                                                          double* __restrict__ bins) {
+    __shared__ double sh[RED_THREADS];
+    const int s = blockIdx.x;
+    const double hi = (s + 0.5) * (s + 0.5);
+    const int64_t per = g.sc, nlines = (int64_t)g.nxk * g.M;
+    double acc = 0.0;
+    for (int64_t l = threadIdx.x; l < nlines; l += RED_THREADS) {
+        const int jx = (int)(l / g.M), jy = (int)(l % g.M);
+        const int kx = g.full ? k_of_j(jx, g) : jx;
+        const int ky = k_of_j(jy, g);
+        const long r2 = (long)kx * kx + (long)ky * ky;
+        if ((double)r2 > hi) continue;   // every mode of the line lies beyond shell s
+        const double lo2 = (s - 0.5) * (s - 0.5) - (double)r2;
+        int a = lo2 > 0.0 ? (int)sqrt(lo2) : 0;
+        a = a > 0 ? a - 1 : 0;
+        while (a <= g.K && shell_of(r2 + (long)a * a) < s) ++a;
+        // half spectrum: 1/2 w |v|^2 (energy); full spectrum: |psi|^2 (number)
+        const double w = g.full ? 1.0 : 0.5 * (kx == 0 ? 1.0 : 2.0);
+        const int64_t line = l * g.M;
+        for (int kz = a; kz <= g.K && shell_of(r2 + (long)kz * kz) == s; ++kz) {
+            for (int sgn = 0; sgn < (kz == 0 ? 1 : 2); ++sgn) {
+                const int jz = sgn == 0 ? kz : g.M - kz;
+                double q = 0.0;
+                for (int c = 0; c < nc; ++c) {
+                    const cx<T> v = st[(int64_t)(c0 + c) * per + line + jz];
+                    q += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+                }
+                acc += w * q;
+            }
         }
-        atomicAdd(&sh[s], 0.5 * (kx == 0 ? 1.0 : 2.0) * a);
     }
+    sh[threadIdx.x] = acc;
     __syncthreads();
-    for (int i = threadIdx.x; i < nshells; i += RED_THREADS)
-        if (sh[i] != 0.0) atomicAdd(&bins[i], sh[i]);
+    for (int h = RED_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bins[s] = sh[0];
 }
 
 // --------------------------------------------------------------- helpers
@@ -264,7 +297,7 @@ static pst_status dalloc(pst_plan* P, void** ptr, size_t bytes) {
 
 static size_t abi_spec_bytes(const pst_plan* P, int ncomp) {
     const size_t n = (size_t)P->p.n;
-    return (size_t)ncomp * n * n * (n / 2 + 1) * P->esz;
+    return (size_t)ncomp * n * n * (P->geo.full ? n : n / 2 + 1) * P->esz;
 }
 
 static pst_status ensure_abi(pst_plan* P, size_t bytes) {
@@ -294,6 +327,18 @@ static pst_status upload_tables(pst_plan* P) {
     }
     HIPCHK(P, hipMemcpy(P->tw, tw.data(), sizeof(cx<T>) * n, hipMemcpyHostToDevice));
     const int nk2 = 3 * K * K + 1;
+    if (P->p.solver == PST_GPE) {
+        // exp(-i alpha |k|^2 h / 2) and its square, by integer |k|^2
+        std::vector<cx<T>> E(nk2), E2(nk2);
+        for (int k2 = 0; k2 < nk2; ++k2) {
+            const double a = P->p.alpha * (double)k2 * P->p.dt;
+            E[k2] = {(T)cos(0.5 * a), (T)(-sin(0.5 * a))};
+            E2[k2] = {(T)cos(a), (T)(-sin(a))};
+        }
+        HIPCHK(P, hipMemcpy(P->Etab[0], E.data(), sizeof(cx<T>) * nk2, hipMemcpyHostToDevice));
+        HIPCHK(P, hipMemcpy(P->E2tab[0], E2.data(), sizeof(cx<T>) * nk2, hipMemcpyHostToDevice));
+        return PST_OK;
+    }
     for (int grp = 0; grp < 2; ++grp) {
         const double visc = grp == 0 ? P->p.nu : P->p.eta;
         std::vector<T> E(nk2), E2(nk2);
@@ -329,18 +374,23 @@ extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst
     if (!out) return fail(nullptr, PST_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!p) return fail(nullptr, PST_ERR_INVALID_ARG, "params is NULL");
-    if (p->solver != PST_NS && p->solver != PST_MHD && p->solver != PST_BOUSSINESQ)
+    if (p->solver != PST_NS && p->solver != PST_MHD && p->solver != PST_BOUSSINESQ && p->solver != PST_GPE)
         return fail(nullptr, PST_ERR_INVALID_ARG, "solver %d", p->solver);
+    const bool gpe = p->solver == PST_GPE;
+    if (gpe && (!isfinite(p->alpha) || !isfinite(p->beta)))
+        return fail(nullptr, PST_ERR_INVALID_ARG, "alpha and beta must be finite");
+    if (gpe && p->dealias != PST_DEALIAS_CUBE)
+        return fail(nullptr, PST_ERR_UNSUPPORTED, "the GPE solver dealiases by the cube only");
     if (p->precision != PST_FP32 && p->precision != PST_FP64)
         return fail(nullptr, PST_ERR_INVALID_ARG, "precision %d", p->precision);
     if (p->rk_order != 2 && p->rk_order != 4) return fail(nullptr, PST_ERR_INVALID_ARG, "rk_order %d", p->rk_order);
     if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(nullptr, PST_ERR_INVALID_ARG, "dt must be > 0");
-    if (!(p->nu >= 0.0) || !isfinite(p->nu)) return fail(nullptr, PST_ERR_INVALID_ARG, "nu must be >= 0");
-    if (p->solver != PST_NS && (!(p->eta >= 0.0) || !isfinite(p->eta)))
+    if (!gpe && (!(p->nu >= 0.0) || !isfinite(p->nu))) return fail(nullptr, PST_ERR_INVALID_ARG, "nu must be >= 0");
+    if ((p->solver == PST_MHD || p->solver == PST_BOUSSINESQ) && (!(p->eta >= 0.0) || !isfinite(p->eta)))
         return fail(nullptr, PST_ERR_INVALID_ARG, "eta must be >= 0");
     if (p->solver == PST_BOUSSINESQ && !isfinite(p->nbv))
         return fail(nullptr, PST_ERR_INVALID_ARG, "nbv must be finite");
-    if (p->dealias != PST_DEALIAS_CUBE && p->dealias != PST_DEALIAS_SPHERE)
+    if (p->dealias != PST_DEALIAS_CUBE && p->dealias != PST_DEALIAS_SPHERE && p->dealias != PST_DEALIAS_NONE)
         return fail(nullptr, PST_ERR_UNSUPPORTED, "dealias %d", p->dealias);
     if (p->flags & ~(unsigned)(PST_FLAG_LINEAR_ONLY | PST_FLAG_TIMERS))
         return fail(nullptr, PST_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
@@ -354,20 +404,25 @@ extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst
     P->stream = (hipStream_t)hip_stream;
     P->L = L;
     P->esz = p->precision == PST_FP64 ? 16 : 8;
-    const int n = p->n, K = (n + 2) / 3 - 1, M = 2 * K + 1;
+    // 2/3 rule: the largest K with 3K < n; NONE keeps every mode but the Nyquist;
+    // GPE (cubic product): the largest K with 4K < n, kx on the full axis
+    const int n = p->n;
+    const int K = gpe ? (n + 3) / 4 - 1 : p->dealias == PST_DEALIAS_NONE ? n / 2 - 1 : (n + 2) / 3 - 1;
+    const int M = 2 * K + 1;
     P->geo.n = n;
     P->geo.K = K;
     P->geo.M = M;
-    P->geo.nxk = K + 1;
-    P->geo.sc = (int64_t)(K + 1) * M * M;
-    P->geo.sa = (int64_t)(K + 1) * M * n;
-    P->geo.sb = (int64_t)(K + 1) * n * n;
+    P->geo.full = gpe ? 1 : 0;
+    P->geo.nxk = gpe ? M : K + 1;
+    P->geo.sc = (int64_t)P->geo.nxk * M * M;
+    P->geo.sa = (int64_t)P->geo.nxk * M * n;
+    P->geo.sb = (int64_t)P->geo.nxk * n * n;
     const bool mhd = p->solver == PST_MHD, bq = p->solver == PST_BOUSSINESQ;
     // state components; fields of the backward passes (v, i k x v per vector
-    // field; grad theta and theta) and of the forward passes
-    P->ncomp = mhd ? 6 : bq ? 4 : 3;
-    P->nfin = mhd ? 12 : bq ? 10 : 6;
-    P->nfout = mhd ? 6 : bq ? 4 : 3;
+    // field; grad theta and theta; psi) and of the forward passes
+    P->ncomp = mhd ? 6 : bq ? 4 : gpe ? 1 : 3;
+    P->nfin = mhd ? 12 : bq ? 10 : gpe ? 1 : 6;
+    P->nfout = mhd ? 6 : bq ? 4 : gpe ? 1 : 3;
     P->kf = -1;
     const size_t es = P->esz, tsz = p->precision == PST_FP64 ? 8 : 4;
     pst_status s = PST_OK;
@@ -389,9 +444,9 @@ extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst
     ALLOC(P->C, (size_t)P->nfout * P->geo.sb * es);
     ALLOC(P->tw, (size_t)n * es);
     const size_t nk2 = 3 * (size_t)K * K + 1;
-    for (int i = 0; i < 2; ++i) {
-        ALLOC(P->Etab[i], nk2 * tsz);
-        ALLOC(P->E2tab[i], nk2 * tsz);
+    for (int i = 0; i < 2; ++i) {   // real factors; GPE: complex ones in the first pair
+        ALLOC(P->Etab[i], nk2 * (gpe ? es : tsz));
+        ALLOC(P->E2tab[i], nk2 * (gpe ? es : tsz));
     }
     ALLOC(P->red, sizeof(double) * (RED_BLOCKS + MAX_SHELLS + 8));
 #undef ALLOC
@@ -427,14 +482,19 @@ extern "C" pst_status pst_query(const pst_plan* P, pst_info* info) {
 
 // --------------------------------------------------------------- state I/O
 static bool valid_field(const pst_plan* P, int field) {
+    if (P->p.solver == PST_GPE) return field == PST_FIELD_PSI;
     return field == PST_FIELD_U || (field == PST_FIELD_B && P->p.solver == PST_MHD) ||
            (field == PST_FIELD_THETA && P->p.solver == PST_BOUSSINESQ);
 }
 // first state component and component count of a field
-static int field_c0(int field) { return field == PST_FIELD_U ? 0 : 3; }
-static int field_nc(int field) { return field == PST_FIELD_THETA ? 1 : 3; }
+static int field_c0(int field) { return field == PST_FIELD_U || field == PST_FIELD_PSI ? 0 : 3; }
+static int field_nc(int field) { return field == PST_FIELD_THETA || field == PST_FIELD_PSI ? 1 : 3; }
 // the fields of the state, in component order
 static int state_fields(const pst_plan* P, int* f) {
+    if (P->p.solver == PST_GPE) {
+        f[0] = PST_FIELD_PSI;
+        return 1;
+    }
     f[0] = PST_FIELD_U;
     if (P->p.solver == PST_MHD) f[1] = PST_FIELD_B;
     else if (P->p.solver == PST_BOUSSINESQ) f[1] = PST_FIELD_THETA;
@@ -474,7 +534,8 @@ extern "C" pst_status pst_set_state(pst_plan* P, int field, int space, const voi
     const size_t n = P->p.n;
     const int nc = field_nc(field);
     const size_t spec = abi_spec_bytes(P, nc);
-    const size_t phys = nc * n * n * n * (P->esz / 2);
+    // physical data: real, or complex for the GPE wavefunction
+    const size_t phys = nc * n * n * n * (P->geo.full ? P->esz : P->esz / 2);
     // layout of the scratch: [spectral (nc comps)] [physical staging if needed]
     const size_t need = spec + ((space == PST_SPACE_PHYS && mem == PST_MEM_HOST) ? phys : 0);
     pst_status s = ensure_abi(P, need);
@@ -492,8 +553,9 @@ extern "C" pst_status pst_set_state(pst_plan* P, int field, int space, const voi
             HIPCHK(P, hipMemcpyAsync(spec_buf + spec, src, phys, hipMemcpyHostToDevice, P->stream));
             phys_dev = spec_buf + spec;
         }
-        P->L->fft_r2c(P, phys_dev, spec_buf, nc);
-        if ((s = check_launch(P, "fft_r2c"))) return s;
+        if (P->geo.full) P->L->fft_c2c(P, phys_dev, spec_buf, nc, 0);
+        else P->L->fft_r2c(P, phys_dev, spec_buf, nc);
+        if ((s = check_launch(P, "forward transform"))) return s;
     }
     char* st = (char*)P->U + (size_t)field_c0(field) * P->geo.sc * P->esz;
     gather(P, spec_buf, st, nc);
@@ -512,7 +574,7 @@ extern "C" pst_status pst_get_state(pst_plan* P, int field, int space, void* dst
     const size_t n = P->p.n;
     const int nc = field_nc(field);
     const size_t spec = abi_spec_bytes(P, nc);
-    const size_t phys = nc * n * n * n * (P->esz / 2);
+    const size_t phys = nc * n * n * n * (P->geo.full ? P->esz : P->esz / 2);
     // scratch: [spectral] [c2r workspace (spectral)] [physical staging]
     const size_t need = space == PST_SPACE_SPEC ? spec : 2 * spec + (mem == PST_MEM_HOST ? phys : 0);
     pst_status s = ensure_abi(P, need);
@@ -530,8 +592,9 @@ extern "C" pst_status pst_get_state(pst_plan* P, int field, int space, void* dst
     } else {
         scatter(P, st, spec_buf, nc);
         void* target = mem == PST_MEM_DEVICE ? dst : (void*)(spec_buf + 2 * spec);
-        P->L->fft_c2r(P, spec_buf, target, nc, spec_buf + spec);
-        if ((s = check_launch(P, "fft_c2r"))) return s;
+        if (P->geo.full) P->L->fft_c2c(P, spec_buf, target, nc, 1);
+        else P->L->fft_c2r(P, spec_buf, target, nc, spec_buf + spec);
+        if ((s = check_launch(P, "backward transform"))) return s;
         if (mem == PST_MEM_HOST) {
             HIPCHK(P, hipMemcpyAsync(dst, target, phys, hipMemcpyDeviceToHost, P->stream));
             HIPCHK(P, hipStreamSynchronize(P->stream));
@@ -596,7 +659,7 @@ static pst_status set_forcing_t(pst_plan* P, const cx<T>* h /*host ABI layout*/)
 
 extern "C" pst_status pst_set_forcing(pst_plan* P, const void* fhat, int mem) {
     if (!P) return PST_ERR_INVALID_ARG;
-    if (P->p.solver == PST_MHD)
+    if (P->p.solver == PST_MHD || P->p.solver == PST_GPE)
         return fail(P, PST_ERR_INVALID_ARG, "forcing is defined for the Navier-Stokes and Boussinesq solvers only");
     if (mem != PST_MEM_HOST && mem != PST_MEM_DEVICE) return fail(P, PST_ERR_INVALID_ARG, "mem %d", mem);
     const size_t bytes = abi_spec_bytes(P, 3);
@@ -678,11 +741,15 @@ extern "C" pst_status pst_step(pst_plan* P, int nsteps) {
 
 // --------------------------------------------------------------- diagnostics
 template <typename T>
-static void launch_energy(pst_plan* P, int c0, int nc, double* out, int k2w) {
+static void launch_energy(pst_plan* P, int c0, int nc, double* out, int k2w, double scale) {
     KTimer tm(P, PST_K_OTHER);
     hipLaunchKernelGGL((k_energy_part<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, P->stream, (const cx<T>*)P->U,
                        P->geo, c0, nc, P->red, k2w);
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(RED_THREADS), 0, P->stream, P->red, RED_BLOCKS, out, 0.5);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(RED_THREADS), 0, P->stream, P->red, RED_BLOCKS, out, scale);
+}
+static void launch_energy_p(pst_plan* P, int c0, int nc, double* out, int k2w, double scale) {
+    if (P->p.precision == PST_FP64) launch_energy<double>(P, c0, nc, out, k2w, scale);
+    else launch_energy<float>(P, c0, nc, out, k2w, scale);
 }
 
 // energy (k2w = 0) or enstrophy (k2w = 1) of u and b
@@ -690,10 +757,15 @@ static pst_status quadratic_diag(pst_plan* P, double out[2], int k2w, const char
     if (!P || !out) return P ? fail(P, PST_ERR_INVALID_ARG, "out is NULL") : PST_ERR_INVALID_ARG;
     double* res = P->red + RED_BLOCKS + MAX_SHELLS;
     int fl[2];
-    const int nfl = state_fields(P, fl);
-    for (int i = 0; i < nfl; ++i) {
-        if (P->p.precision == PST_FP64) launch_energy<double>(P, field_c0(fl[i]), field_nc(fl[i]), res + i, k2w);
-        else launch_energy<float>(P, field_c0(fl[i]), field_nc(fl[i]), res + i, k2w);
+    int nfl = state_fields(P, fl);
+    if (P->p.solver == PST_GPE) {
+        // energy: particle number and kinetic energy alpha sum |k|^2 |psi|^2;
+        // enstrophy: sum |k|^2 |psi|^2 alone
+        launch_energy_p(P, 0, 1, res, k2w, 1.0);
+        if (!k2w) launch_energy_p(P, 0, 1, res + 1, 1, P->p.alpha);
+        nfl = k2w ? 1 : 2;
+    } else {
+        for (int i = 0; i < nfl; ++i) launch_energy_p(P, field_c0(fl[i]), field_nc(fl[i]), res + i, k2w, 0.5);
     }
     pst_status s = check_launch(P, what);
     if (s) return s;
@@ -719,15 +791,14 @@ extern "C" pst_status pst_spectrum(pst_plan* P, int field, double* Ek, int nshel
     if (nshells < need || nshells > MAX_SHELLS)
         return fail(P, PST_ERR_INVALID_ARG, "nshells must be in [%d, %d]", need, MAX_SHELLS);
     double* bins = P->red + RED_BLOCKS;
-    HIPCHK(P, hipMemsetAsync(bins, 0, sizeof(double) * nshells, P->stream));
     {
         KTimer tm(P, PST_K_OTHER);
         if (P->p.precision == PST_FP64)
-            hipLaunchKernelGGL((k_spectrum<double>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, P->stream,
-                               (const cx<double>*)P->U, P->geo, field_c0(field), field_nc(field), bins, nshells);
+            hipLaunchKernelGGL((k_spectrum<double>), dim3(nshells), dim3(RED_THREADS), 0, P->stream,
+                               (const cx<double>*)P->U, P->geo, field_c0(field), field_nc(field), bins);
         else
-            hipLaunchKernelGGL((k_spectrum<float>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, P->stream,
-                               (const cx<float>*)P->U, P->geo, field_c0(field), field_nc(field), bins, nshells);
+            hipLaunchKernelGGL((k_spectrum<float>), dim3(nshells), dim3(RED_THREADS), 0, P->stream,
+                               (const cx<float>*)P->U, P->geo, field_c0(field), field_nc(field), bins);
     }
     pst_status s = check_launch(P, "spectrum");
     if (s) return s;

@@ -28,11 +28,11 @@ lib = ctypes.CDLL(LIB_PATH)
 # ------------------------------------------------------------------ ABI types
 PST_OK, PST_ERR_INVALID_ARG, PST_ERR_UNSUPPORTED_N, PST_ERR_OOM, PST_ERR_HIP, PST_ERR_NONFINITE, \
     PST_ERR_UNSUPPORTED = range(7)
-PST_NS, PST_MHD, PST_BOUSSINESQ = 0, 1, 2
+PST_NS, PST_MHD, PST_BOUSSINESQ, PST_GPE = 0, 1, 2, 3
 PST_FP32, PST_FP64 = 0, 1
-PST_FIELD_U, PST_FIELD_B, PST_FIELD_THETA = 0, 1, 2
-_FIELDS = {"u": PST_FIELD_U, "b": PST_FIELD_B, "theta": PST_FIELD_THETA}
-_SOLVERS = {"ns": PST_NS, "mhd": PST_MHD, "boussinesq": PST_BOUSSINESQ}
+PST_FIELD_U, PST_FIELD_B, PST_FIELD_THETA, PST_FIELD_PSI = 0, 1, 2, 3
+_FIELDS = {"u": PST_FIELD_U, "b": PST_FIELD_B, "theta": PST_FIELD_THETA, "psi": PST_FIELD_PSI}
+_SOLVERS = {"ns": PST_NS, "mhd": PST_MHD, "boussinesq": PST_BOUSSINESQ, "gpe": PST_GPE}
 PST_SPACE_PHYS, PST_SPACE_SPEC = 0, 1
 PST_MEM_HOST, PST_MEM_DEVICE = 0, 1
 PST_FLAG_LINEAR_ONLY, PST_FLAG_TIMERS = 1, 2
@@ -43,7 +43,7 @@ class pst_params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("solver", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rk_order", ctypes.c_int), ("nu", ctypes.c_double), ("eta", ctypes.c_double),
                 ("dt", ctypes.c_double), ("dealias", ctypes.c_int), ("flags", ctypes.c_uint),
-                ("nbv", ctypes.c_double)]
+                ("nbv", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 class pst_info(ctypes.Structure):
@@ -82,7 +82,8 @@ _ens_sigs = [("pst_ensemble_create", [_I, _P, ctypes.POINTER(pst_params), _P, ct
              ("pst_ensemble_energy", [_P, _P]), ("pst_ensemble_autotune", [_P, ctypes.c_char_p, _I, _P]),
              ("pst_ensemble_set_schedule", [_P, _I]), ("pst_ensemble_query", [_P, _P, _P, _P, _P, _P]),
              ("pst_ensemble_project", [_P]), ("pst_ensemble_diagnostics", [_P, _P, _P]),
-             ("pst_ensemble_rel_l2", [_P, _P, _P])]
+             ("pst_ensemble_rel_l2", [_P, _P, _P]),
+             ("pst_ensemble_set_spin_limit", [_P, ctypes.c_longlong])]
 for _name, _args in _ens_sigs:
     getattr(lib, _name).argtypes = _args
     getattr(lib, _name).restype = _S
@@ -117,7 +118,7 @@ EXPORTED = ["pst_fno_create", "pst_fno_destroy", "pst_fno_last_error", "pst_fno_
             "pst_ensemble_get_state", "pst_ensemble_step", "pst_ensemble_set_mode", "pst_ensemble_get_mode",
             "pst_ensemble_energy",
             "pst_ensemble_autotune", "pst_ensemble_set_schedule", "pst_ensemble_query", "pst_ensemble_project",
-            "pst_ensemble_diagnostics", "pst_ensemble_rel_l2",
+            "pst_ensemble_diagnostics", "pst_ensemble_rel_l2", "pst_ensemble_set_spin_limit",
             "pst_status_str", "pst_last_error", "pst_supported_n", "pst_plan_create", "pst_plan_destroy",
             "pst_set_state", "pst_get_state", "pst_set_forcing", "pst_rhs", "pst_step", "pst_energy", "pst_enstrophy",
             "pst_spectrum", "pst_fft_r2c", "pst_fft_c2r", "pst_query", "pst_timer_read"]
@@ -153,26 +154,49 @@ def _ptr(x):
     return ctypes.c_void_p(x.data_ptr()), (PST_MEM_DEVICE if x.is_cuda else PST_MEM_HOST)
 
 
+def _check_buf(x, dtype, numel, what, device=None):
+    """Validate a buffer handed to a C call that reads or writes a fixed byte
+    count: element type, element count, contiguity and (device=True) that a
+    torch tensor lives on the GPU.  Raises ValueError on a mismatch."""
+    if isinstance(x, np.ndarray):
+        if device:
+            raise ValueError(f"{what}: expected a device tensor, got a numpy array")
+        if x.dtype != np.dtype(dtype):
+            raise ValueError(f"{what}: dtype {x.dtype}, expected {np.dtype(dtype)}")
+        n = x.size
+    else:
+        if device is not None and bool(x.is_cuda) != bool(device):
+            raise ValueError(f"{what}: tensor on {x.device}, expected {'a GPU' if device else 'the host'}")
+        if _np_dtype(x) != np.dtype(dtype):
+            raise ValueError(f"{what}: dtype {x.dtype}, expected {np.dtype(dtype)}")
+        n = x.numel()
+    if n != numel:
+        raise ValueError(f"{what}: {n} elements, expected {numel}")
+
+
 class Plan:
     """One solver plan (pst_plan_create ... pst_plan_destroy)."""
 
     def __init__(self, n, solver="ns", precision="fp32", rk_order=4, nu=0.0, eta=None, dt=1e-3,
-                 linear_only=False, timers=False, stream=None, dealias="cube", kappa=None, nbv=0.0):
-        """solver: "ns", "mhd" (eta: magnetic diffusivity) or "boussinesq"
-        (kappa: scalar diffusivity, default nu; nbv: Brunt-Vaisala frequency)."""
+                 linear_only=False, timers=False, stream=None, dealias="cube", kappa=None, nbv=0.0,
+                 alpha=0.0, beta=0.0):
+        """solver: "ns", "mhd" (eta: magnetic diffusivity), "boussinesq"
+        (kappa: scalar diffusivity, default nu; nbv: Brunt-Vaisala frequency)
+        or "gpe" (d psi/dt = i alpha Lap psi - i beta |psi|^2 psi)."""
         second = kappa if solver == "boussinesq" else eta
         p = pst_params(n=n, solver=_SOLVERS[solver],
                        precision=PST_FP64 if precision == "fp64" else PST_FP32, rk_order=rk_order,
                        nu=nu, eta=nu if second is None else second, dt=dt,
-                       dealias={"cube": 0, "sphere": 1}[dealias],
+                       dealias={"cube": 0, "sphere": 1, "none": 2}[dealias],
                        flags=(PST_FLAG_LINEAR_ONLY if linear_only else 0) | (PST_FLAG_TIMERS if timers else 0),
-                       nbv=nbv)
+                       nbv=nbv, alpha=alpha, beta=beta)
         self.params = p
         self.n = n
         self.fp64 = precision == "fp64"
         self.mhd = solver == "mhd"
         self.solver = solver
-        self.ncomp = {"ns": 3, "mhd": 6, "boussinesq": 4}[solver]
+        self.ncomp = {"ns": 3, "mhd": 6, "boussinesq": 4, "gpe": 1}[solver]
+        self.gpe = solver == "gpe"
         self.real_np = np.float64 if self.fp64 else np.float32
         self.cplx_np = np.complex128 if self.fp64 else np.complex64
         h = _P()
@@ -202,32 +226,51 @@ class Plan:
         return self._h
 
     def spec_shape(self, ncomp=3):
-        return (ncomp, self.n, self.n, self.n // 2 + 1)
+        # GPE: the whole spectrum of a complex field
+        return (ncomp, self.n, self.n, self.n if self.gpe else self.n // 2 + 1)
 
     def phys_shape(self, ncomp=3):
         return (ncomp, self.n, self.n, self.n)
 
+    def _phys_np(self):
+        return self.cplx_np if self.gpe else self.real_np
+
+    def _field_nc(self, field):
+        return 1 if field in ("theta", "psi") else 3
+
     # --------------------------------------------------------------- ABI calls
-    def set_state(self, data, field="u", space=None):
+    def set_state(self, data, field=None, space=None):
         """data: numpy (host) or torch (device) array, spectral complex
         [nc][n][n][n/2+1] or physical real [nc][n][n][n] (nc = 3 for u and b,
-        1 for theta, which may also be given without the leading axis)."""
+        1 for theta, which may also be given without the leading axis).  GPE
+        (field psi): spectral complex [1][n][n][n], physical complex
+        [1][n][n][n]; space must then be given for physical data."""
+        if field is None:
+            field = "psi" if self.gpe else "u"
         f = _FIELDS[field]
         if space is None:
-            space = "spec" if np.iscomplexobj(np.empty(0, dtype=_np_dtype(data))) else "phys"
+            space = "spec" if (self.gpe or np.iscomplexobj(np.empty(0, dtype=_np_dtype(data)))) else "phys"
+        pdt = self.cplx_np if space == "spec" else self._phys_np()
         if isinstance(data, np.ndarray):
-            data = np.ascontiguousarray(data, self.cplx_np if space == "spec" else self.real_np)
+            data = np.ascontiguousarray(data, pdt)
+        nc = self._field_nc(field)
+        shape = self.spec_shape(nc) if space == "spec" else self.phys_shape(nc)
+        _check_buf(data, pdt, int(np.prod(shape)), "set_state")
         ptr, mem = _ptr(data)
         self._check(lib.pst_set_state(self._h, f, PST_SPACE_SPEC if space == "spec" else PST_SPACE_PHYS,
                                       ptr, mem))
 
-    def get_state(self, field="u", space="spec", out=None):
+    def get_state(self, field=None, space="spec", out=None):
+        if field is None:
+            field = "psi" if self.gpe else "u"
         f = _FIELDS[field]
         sp = PST_SPACE_SPEC if space == "spec" else PST_SPACE_PHYS
-        nc = 1 if field == "theta" else 3
+        nc = self._field_nc(field)
+        pdt = self.cplx_np if space == "spec" else self._phys_np()
+        shape = self.spec_shape(nc) if space == "spec" else self.phys_shape(nc)
         if out is None:
-            out = np.empty(self.spec_shape(nc) if space == "spec" else self.phys_shape(nc),
-                           self.cplx_np if space == "spec" else self.real_np)
+            out = np.empty(shape, pdt)
+        _check_buf(out, pdt, int(np.prod(shape)), "get_state")
         ptr, mem = _ptr(out)
         self._check(lib.pst_get_state(self._h, f, sp, ptr, mem))
         return out
@@ -238,10 +281,14 @@ class Plan:
             return
         if isinstance(fhat, np.ndarray):
             fhat = np.ascontiguousarray(fhat, self.cplx_np)
+        _check_buf(fhat, self.cplx_np, int(np.prod(self.spec_shape(3))), "set_forcing")
         ptr, mem = _ptr(fhat)
         self._check(lib.pst_set_forcing(self._h, ptr, mem))
 
     def rhs(self, state_dev, rhs_dev):
+        m = int(np.prod(self.spec_shape(self.ncomp)))
+        _check_buf(state_dev, self.cplx_np, m, "rhs state", device=True)
+        _check_buf(rhs_dev, self.cplx_np, m, "rhs output", device=True)
         a, _ = _ptr(state_dev)
         b, _ = _ptr(rhs_dev)
         self._check(lib.pst_rhs(self._h, a, b))
@@ -259,19 +306,25 @@ class Plan:
         self._check(lib.pst_enstrophy(self._h, out.ctypes.data_as(_P)))
         return float(out[0]), float(out[1])
 
-    def spectrum(self, field="u", nshells=None):
+    def spectrum(self, field=None, nshells=None):
+        if field is None:
+            field = "psi" if self.gpe else "u"
         if nshells is None:
-            nshells = int(np.floor(np.sqrt(3.0) * kcut_23(self.n) + 0.5)) + 1
+            nshells = int(np.floor(np.sqrt(3.0) * self.query()["kcut"] + 0.5)) + 1
         out = np.zeros(nshells, np.float64)
         self._check(lib.pst_spectrum(self._h, _FIELDS[field], out.ctypes.data_as(_P), nshells))
         return out
 
     def fft_r2c(self, x, out, nfields):
+        _check_buf(x, self.real_np, nfields * int(np.prod(self.phys_shape(1))), "fft_r2c input", device=True)
+        _check_buf(out, self.cplx_np, nfields * int(np.prod(self.spec_shape(1))), "fft_r2c output", device=True)
         a, _ = _ptr(x)
         b, _ = _ptr(out)
         self._check(lib.pst_fft_r2c(self._h, a, b, nfields))
 
     def fft_c2r(self, x, out, nfields):
+        _check_buf(x, self.cplx_np, nfields * int(np.prod(self.spec_shape(1))), "fft_c2r input", device=True)
+        _check_buf(out, self.real_np, nfields * int(np.prod(self.phys_shape(1))), "fft_c2r output", device=True)
         a, _ = _ptr(x)
         b, _ = _ptr(out)
         self._check(lib.pst_fft_c2r(self._h, a, b, nfields))
@@ -332,9 +385,16 @@ class Ensemble:
         except Exception:
             pass
 
+    def _check_run_buf(self, run, buf, what):
+        # an out-of-range run is left to the library, which reports it
+        if 0 <= run < len(self.sizes):
+            n = self.sizes[run]
+            _check_buf(buf, np.complex64, 3 * n * n * (n // 2 + 1), what)
+
     def set_state(self, run, uhat):
         if isinstance(uhat, np.ndarray):
             uhat = np.ascontiguousarray(uhat, np.complex64)
+        self._check_run_buf(run, uhat, "ensemble set_state")
         ptr, mem = _ptr(uhat)
         self._check(lib.pst_ensemble_set_state(self._h, run, ptr, mem))
 
@@ -342,6 +402,7 @@ class Ensemble:
         n = self.sizes[run]
         if out is None:
             out = np.empty((3, n, n, n // 2 + 1), np.complex64)
+        self._check_run_buf(run, out, "ensemble get_state")
         ptr, mem = _ptr(out)
         self._check(lib.pst_ensemble_get_state(self._h, run, ptr, mem))
         return out
@@ -379,6 +440,10 @@ class Ensemble:
 
     def set_schedule(self, variant):
         self._check(lib.pst_ensemble_set_schedule(self._h, variant))
+
+    def set_spin_limit(self, polls):
+        """Test only: polls of a device-wide barrier before it reports a timeout."""
+        self._check(lib.pst_ensemble_set_spin_limit(self._h, int(polls)))
 
     def get_mode(self):
         m = ctypes.c_int(-1)
@@ -441,10 +506,22 @@ class FNO:
         self._check(lib.pst_fno_get_grad(self._h, out.ctypes.data_as(_P), PST_MEM_HOST))
         return out
 
+    def _check_io(self, u, other, what):
+        b = u.shape[0] if u.dim() >= 1 else 0
+        if not 1 <= b <= self.batch:
+            raise ValueError(f"batch {b} outside 1..{self.batch}")
+        n = self.cfg["n"]
+        numel = b * 3 * n ** 3
+        _check_buf(u, np.float32, numel, "fno input", device=True)
+        _check_buf(other, np.float32, numel, what, device=True)
+        return b
+
     def forward(self, u, out):
-        self._check(lib.pst_fno_forward(self._h, _ptr(u)[0], _ptr(out)[0], u.shape[0]))
+        b = self._check_io(u, out, "fno output")
+        self._check(lib.pst_fno_forward(self._h, _ptr(u)[0], _ptr(out)[0], b))
 
     def loss_grad(self, u, tgt):
+        self._check_io(u, tgt, "fno target")
         L = ctypes.c_double()
         self._check(lib.pst_fno_loss_grad(self._h, _ptr(u)[0], _ptr(tgt)[0], u.shape[0], ctypes.byref(L)))
         return L.value
@@ -453,6 +530,7 @@ class FNO:
         self._check(lib.pst_fno_adam(self._h, lr, beta1, beta2, eps))
 
     def train_step(self, u, tgt, lr):
+        self._check_io(u, tgt, "fno target")
         L = ctypes.c_double()
         self._check(lib.pst_fno_train_step(self._h, _ptr(u)[0], _ptr(tgt)[0], u.shape[0], lr, ctypes.byref(L)))
         return L.value

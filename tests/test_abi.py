@@ -60,7 +60,7 @@ def _create(pst, **kw):
     (dict(solver=5), 1), (dict(precision=3), 1), (dict(rk_order=3), 1),
     (dict(dt=0.0), 1), (dict(dt=-1.0), 1), (dict(nu=-1.0), 1), (dict(nu=float("nan")), 1),
     (dict(solver=1, eta=-2.0), 1), (dict(solver=2, eta=-1.0), 1), (dict(solver=2, nbv=float("inf")), 1),
-    (dict(dealias=2), 6), (dict(flags=0x100), 1),
+    (dict(dealias=3), 6), (dict(flags=0x100), 1),
 ])
 def test_plan_create_rejects_bad_params(pst, kw, status):
     s, h = _create(pst, **kw)

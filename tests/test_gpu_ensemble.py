@@ -171,3 +171,28 @@ def test_project_diagnostics_distance(O, P):
     for r in range(len(sizes)):
         a = ens.get_state(r).astype(np.complex128)
         assert abs(d[r] - np.sqrt(O.energy(a - states[r]) / O.energy(states[r]))) < 1e-6
+
+
+@pytest.mark.parametrize("mode", ["graph", "persistent"])
+def test_barrier_timeout_reported_over_steps(P, init, ref, mode):
+    """A device-wide barrier that times out in any step of a multi-step call is
+    reported (the flag is not cleared by the later steps).  The timeout is
+    forced from the host with a zero poll limit, so every kernel exits
+    normally; afterwards, with the default limit restored and the state
+    reloaded, the same ensemble steps correctly again (the flag was cleared)."""
+    ens = P.Ensemble(SIZES, rk_order=RK, nu=NU, dt=DT)
+    try:
+        ens.set_mode(mode)
+        for r, u in enumerate(init):
+            ens.set_state(r, u)
+        ens.set_spin_limit(0)
+        with pytest.raises(P.PstError, match="timed out"):
+            ens.step(3)
+        ens.set_spin_limit(1 << 22)
+        for r, u in enumerate(init):
+            ens.set_state(r, u)
+        ens.step(NSTEPS)
+        for r in range(len(SIZES)):
+            assert rel(ens.get_state(r), ref[r]) < 1e-5, (mode, r)
+    finally:
+        ens.close()

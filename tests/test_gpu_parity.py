@@ -165,6 +165,31 @@ def test_sphere_truncation(O, P, torch, n, prec):
     assert max(rel_per_field(got[3:], rb)) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [16, 24, 48])
+def test_dealias_none(O, P, torch, n, prec):
+    """Dealias NONE (test only): every mode but the Nyquist is kept, so the
+    products alias.  Against the oracle with the cutoff n/2 - 1 on every axis
+    (right-hand side and two RK4 steps), and visibly different from the 2/3
+    rule on the same input."""
+    kc = n // 2 - 1
+    u = I.random_solenoidal(n, 70 + n, kcut=kc)
+    plan = P.Plan(n, precision=prec, dealias="none")
+    assert plan.query()["kcut"] == kc
+    got = _rhs(P, torch, plan, u)
+    ref = O.ns_rhs(u, kcut=kc)
+    assert max(rel_per_field(got, ref)) < TOL[prec]
+    # the 2/3 rule on the band-limited part of the same field removes the aliases
+    u23 = u * I.cube_mask(n)[None]
+    assert rel(O.ns_rhs(u23, kcut=kc), O.ns_rhs(u23)) > 1e-4
+    nu, dt = 0.02, 2e-3
+    plan = P.Plan(n, precision=prec, rk_order=4, nu=nu, dt=dt, dealias="none")
+    plan.set_state(u)
+    plan.step(2)
+    ref = O.step(u, 2, dt=dt, nu=nu, rk=4, kcut=kc)
+    assert max(rel_per_field(plan.get_state(), ref)) < TOL[prec]
+
+
 def test_taylor_green_closed_form_on_gpu(P, torch):
     n = 32
     plan = P.Plan(n, precision="fp64")
@@ -283,15 +308,28 @@ def test_mhd_enstrophy(O, P, torch):
     assert abs(zb - O.enstrophy(plan.get_state("b"))) < 1e-13 * zb
 
 
-def test_bitwise_repeatable(P, torch):
+@pytest.mark.parametrize("solver", ["ns", "mhd"])
+def test_bitwise_repeatable(P, torch, solver):
+    """Two plans from the same input give bitwise the same state after three
+    steps, and bitwise the same energy, enstrophy and shell spectrum (every
+    reduction sums in a fixed order), also when a diagnostic is repeated."""
     n = 48
-    outs = []
+    outs, diags = [], []
     for _ in range(2):
-        plan = P.Plan(n, precision="fp32", rk_order=4, nu=0.02, dt=2e-3)
+        plan = P.Plan(n, solver=solver, precision="fp32", rk_order=4, nu=0.02, dt=2e-3)
         plan.set_state(I.random_solenoidal(n, 5))
+        if solver == "mhd":
+            plan.set_state(I.random_solenoidal(n, 5, field=1, spectrum=I.spectrum_c3, energy=0.5), "b")
         plan.step(3)
         outs.append(plan.get_state())
+        d = [plan.energy(), plan.enstrophy(), plan.spectrum("u")]
+        if solver == "mhd":
+            d.append(plan.spectrum("b"))
+        d2 = [plan.energy(), plan.enstrophy(), plan.spectrum("u")]
+        assert all(np.array_equal(np.asarray(a), np.asarray(b)) for a, b in zip(d, d2))
+        diags.append(d)
     assert np.array_equal(outs[0], outs[1])
+    assert all(np.array_equal(np.asarray(a), np.asarray(b)) for a, b in zip(diags[0], diags[1]))
 
 
 def test_resume_identity(P, torch):
