@@ -214,6 +214,24 @@ pst_status pst_spectrum(pst_plan *plan, int field, double *Ek, int nshells);
 pst_status pst_fft_r2c(pst_plan *plan, const void *in, void *out, int nfields);
 pst_status pst_fft_c2r(pst_plan *plan, const void *in, void *out, int nfields);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * transform of pst_fft_c2r without a plan and without any allocation.  in:
+ * complex [nfields][n][n][n/2+1], out: real [nfields][n][n][n] (device, the
+ * element type of precision), on hip_stream (may be NULL).  The n roots of
+ * unity (regenerated every call in FP64, rounded once) and the pass workspace
+ * live in a static device array of PST_NOALLOC_SCRATCH_BYTES per GPU, held
+ * until the process ends; pst_fft_c2r_noalloc_bytes(n, precision, nfields)
+ * gives what a call needs (0 for invalid arguments) and calls needing more
+ * than the limit fail with INVALID_ARG (e.g. n = 128 takes up to 3 FP64 or 7
+ * FP32 fields, n = 256 is refused).  Nothing in the array needs to start at
+ * zero.  Every call on one GPU shares that GPU's array: calls that overlap on
+ * one GPU (other streams, other host threads) race and must be serialised by
+ * the caller.  Stream-ordered; errors are reported through pst_last_error(NULL). */
+#define PST_NOALLOC_SCRATCH_BYTES (64u << 20)
+size_t pst_fft_c2r_noalloc_bytes(int n, int precision, int nfields);
+pst_status pst_fft_c2r_noalloc(int n, int precision, const void *in, void *out, int nfields, void *hip_stream);
+
 /* Sizes and schedule of the plan. */
 pst_status pst_query(const pst_plan *plan, pst_info *info);
 

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "fft_engine.h"
@@ -85,6 +86,95 @@ extern "C" int pst_supported_n(int n) {
         case 16: case 24: case 32: case 48: case 64: case 96: case 128: case 256: case 512: case 1024: return 1;
         default: return 0;
     }
+}
+
+// --------------------------------------------------------------- c2r without allocation
+// Device memory of pst_fft_c2r_noalloc: the n roots of unity followed by the
+// workspace of the z and y passes.  One copy per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in: kernels are given
+// the per-device address from hipGetSymbolAddress, never the symbol itself.
+static __device__ __align__(256) unsigned char scratch[PST_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEV];
+
+// Address of this device's copy of `scratch` (looked up once per device,
+// with that device current).
+pst_status scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEV)
+        return fail(nullptr, PST_ERR_HIP, "no current HIP device (or device index %d too large)", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(nullptr, PST_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PST_OK;
+}
+}  // namespace
+
+// tw[m] = exp(-2 pi i m / n), evaluated in FP64 and rounded once to T
+template <typename T>
+__global__ void k_roots(cx<T>* __restrict__ tw, int n) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)n, &sn, &cs);
+    tw[m] = {(T)cs, (T)(-sn)};
+}
+
+extern "C" size_t pst_fft_c2r_noalloc_bytes(int n, int precision, int nfields) {
+    if (!pst_supported_n(n) || (precision != PST_FP32 && precision != PST_FP64) || nfields < 1) return 0;
+    const size_t es = precision == PST_FP64 ? 16 : 8, un = (size_t)n;
+    const size_t tw = (un * es + 255) / 256 * 256;
+    return tw + (size_t)nfields * un * un * (un / 2 + 1) * es;
+}
+
+extern "C" pst_status pst_fft_c2r_noalloc(int n, int precision, const void* in, void* out, int nfields,
+                                          void* hip_stream) {
+    if (!in || !out) return fail(nullptr, PST_ERR_INVALID_ARG, "NULL buffer");
+    if (precision != PST_FP32 && precision != PST_FP64)
+        return fail(nullptr, PST_ERR_INVALID_ARG, "precision %d", precision);
+    if (nfields < 1) return fail(nullptr, PST_ERR_INVALID_ARG, "nfields < 1");
+    if (!pst_supported_n(n)) return fail(nullptr, PST_ERR_UNSUPPORTED_N, "n = %d not supported", n);
+    const size_t need = pst_fft_c2r_noalloc_bytes(n, precision, nfields);
+    if (need > (size_t)PST_NOALLOC_SCRATCH_BYTES)
+        return fail(nullptr, PST_ERR_INVALID_ARG,
+                    "n = %d with %d field(s) needs %zu bytes of scratch; the limit is %zu", n, nfields, need,
+                    (size_t)PST_NOALLOC_SCRATCH_BYTES);
+    const Launchers* L = launchers_for(n, precision);
+    if (!L) return fail(nullptr, PST_ERR_UNSUPPORTED_N, "n = %d has no kernels", n);
+    void* base = nullptr;
+    pst_status s = scratch_address(&base);
+    if (s) return s;
+    const size_t es = precision == PST_FP64 ? 16 : 8;
+    void* tmp = (unsigned char*)base + (need - (size_t)nfields * n * n * (n / 2 + 1) * es);
+    // a plan shell on the stack: the launchers read only the stream, the
+    // twiddle pointer and the (cleared) timer flag from it
+    pst_plan Q{};
+    Q.p.n = n;
+    Q.p.precision = precision;
+    Q.p.flags = 0;
+    Q.stream = (hipStream_t)hip_stream;
+    Q.tw = base;
+    Q.esz = es;
+    if (precision == PST_FP64)
+        hipLaunchKernelGGL(k_roots<double>, dim3((n + 255) / 256), dim3(256), 0, Q.stream, (cx<double>*)base, n);
+    else
+        hipLaunchKernelGGL(k_roots<float>, dim3((n + 255) / 256), dim3(256), 0, Q.stream, (cx<float>*)base, n);
+    // every element of the workspace is written by the z pass before it is read
+    L->fft_c2r(&Q, in, out, nfields, tmp);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, PST_ERR_HIP, "fft_c2r_noalloc: kernel launch failed: %s", hipGetErrorString(e));
+    return PST_OK;
 }
 
 // --------------------------------------------------------------- timers

@@ -75,6 +75,11 @@ for _name, _args in [("pst_set_state", [_P, _I, _I, _P, _I]), ("pst_get_state", 
     getattr(lib, _name).argtypes = _args
     getattr(lib, _name).restype = _S
 
+lib.pst_fft_c2r_noalloc.argtypes = [_I, _I, _P, _P, _I, _P]
+lib.pst_fft_c2r_noalloc.restype = _S
+lib.pst_fft_c2r_noalloc_bytes.argtypes = [_I, _I, _I]
+lib.pst_fft_c2r_noalloc_bytes.restype = ctypes.c_size_t
+
 _ens_sigs = [("pst_ensemble_create", [_I, _P, ctypes.POINTER(pst_params), _P, ctypes.POINTER(_P)]),
              ("pst_ensemble_set_state", [_P, _I, _P, _I]), ("pst_ensemble_get_state", [_P, _I, _P, _I]),
              ("pst_ensemble_step", [_P, _I]), ("pst_ensemble_set_mode", [_P, _I]),
@@ -121,7 +126,8 @@ EXPORTED = ["pst_fno_create", "pst_fno_destroy", "pst_fno_last_error", "pst_fno_
             "pst_ensemble_diagnostics", "pst_ensemble_rel_l2", "pst_ensemble_set_spin_limit",
             "pst_status_str", "pst_last_error", "pst_supported_n", "pst_plan_create", "pst_plan_destroy",
             "pst_set_state", "pst_get_state", "pst_set_forcing", "pst_rhs", "pst_step", "pst_energy", "pst_enstrophy",
-            "pst_spectrum", "pst_fft_r2c", "pst_fft_c2r", "pst_query", "pst_timer_read"]
+            "pst_spectrum", "pst_fft_r2c", "pst_fft_c2r", "pst_query", "pst_timer_read",
+            "pst_fft_c2r_noalloc", "pst_fft_c2r_noalloc_bytes"]
 
 
 class PstError(RuntimeError):
@@ -342,6 +348,24 @@ class Plan:
         cnt = np.zeros(len(KERNEL_KINDS), np.int64)
         self._check(lib.pst_timer_read(self._h, ms.ctypes.data_as(_P), cnt.ctypes.data_as(_P), int(reset)))
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def fft_c2r_noalloc(n, x, out, nfields, precision="fp32", stream=None):
+    """pst_fft_c2r_noalloc: the unpruned 3D c2r transform of nfields fields
+    without a plan or any device allocation (its workspace is the library's
+    static per-GPU scratch array; calls overlapping on one GPU race)."""
+    fp64 = precision == "fp64"
+    cn, rn = (np.complex128, np.float64) if fp64 else (np.complex64, np.float32)
+    _check_buf(x, cn, nfields * n * n * (n // 2 + 1), "fft_c2r_noalloc input", device=True)
+    _check_buf(out, rn, nfields * n * n * n, "fft_c2r_noalloc output", device=True)
+    s = lib.pst_fft_c2r_noalloc(n, PST_FP64 if fp64 else PST_FP32, _ptr(x)[0], _ptr(out)[0], nfields,
+                                _P(_stream_handle(stream)))
+    if s != PST_OK:
+        raise PstError(s, lib.pst_last_error(None).decode())
+
+
+def fft_c2r_noalloc_bytes(n, nfields, precision="fp32"):
+    return int(lib.pst_fft_c2r_noalloc_bytes(n, PST_FP64 if precision == "fp64" else PST_FP32, nfields))
 
 
 def _np_dtype(x):
