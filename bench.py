@@ -14,8 +14,10 @@ the mean over the timed steps, the per-step median is reported too.
 Prints one JSON line.  Also reported (under "extra"): a plain device copy's
 bandwidth; the standalone 3D r2c / c2r transforms of 3 fields at 512^3 per pass
 in GB/s; the MHD 1024^3 RK2 step; the 96-run ensemble in every execution mode;
-the FNO's forward pass and training step at 64^3; the surrogate's speed-up
-(from its committed run unless --surrogate); the roofline of the dominant
+the FNO's forward pass and training step at 64^3; the surrogate pipeline run
+live (its speed-up over the whole rollout and over the horizon in which it
+stays within 1e-2 of the plain solver); the Boussinesq 512^3, Gross-Pitaevskii
+512^3 and anisotropic 1024 x 1024 x 256 legs; the roofline of the dominant
 kernel (algorithmic bytes per launch / HIP-event-timed launch duration, as a
 fraction of 8 TB/s and of the copy bandwidth) and the FP64 CPU oracle timed on
 one step on this host.
@@ -52,24 +54,31 @@ def parse():
     ap.add_argument("--no-fno", action="store_true")
     ap.add_argument("--no-mhd", action="store_true")
     ap.add_argument("--no-bq", action="store_true")
-    ap.add_argument("--surrogate", action="store_true",
-                    help="run the whole surrogate pipeline (data, ~70 s of training, evaluation, timed "
-                         "hybrid rollout) instead of reporting its committed summary")
+    ap.add_argument("--no-gpe", action="store_true")
+    ap.add_argument("--no-aniso", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="report the surrogate's committed summary instead of running its pipeline (data, "
+                         "about 20 s of training, evaluation, timed hybrid rollout) live")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counter scaling)")
     return ap.parse_args()
 
 
-def kernel_bytes(n, esz, rk, mhd=False, bq=False):
+def kernel_bytes(n, esz, rk, mhd=False, bq=False, gpe=False, shape=None):
     """Algorithmic HBM bytes per launch of each solver kernel: every array
     element a pass must read or write, once.  State components / backward
     fields / forward fields: 3 / 6 / 3 (Navier-Stokes), 6 / 12 / 6 (MHD),
-    4 / 10 / 4 (Boussinesq: u, theta; v, i k x v, grad theta, theta)."""
-    K = -(-n // 3) - 1
-    M, nxk = 2 * K + 1, K + 1
-    sc, sa, sb = nxk * M * M, nxk * M * n, nxk * n * n
+    4 / 10 / 4 (Boussinesq: u, theta; v, i k x v, grad theta, theta), 1 / 1 / 1
+    (Gross-Pitaevskii: psi on the whole spectrum, cutoff ceil(n/4) - 1).
+    shape = (nx, ny, nz): per-axis sizes and cutoffs."""
+    nx, ny, nz = (n, n, n) if shape is None else shape
+    cut = (lambda m: -(-m // 4) - 1) if gpe else (lambda m: -(-m // 3) - 1)
+    Kx, Ky, Kz = cut(nx), cut(ny), cut(nz)
+    My, Mz = 2 * Ky + 1, 2 * Kz + 1
+    nxk = 2 * Kx + 1 if gpe else Kx + 1
+    sc, sa, sb = nxk * My * Mz, nxk * My * nz, nxk * ny * nz
     rk_arrays = 13.0 / 4.0 if rk == 4 else 5.0 / 2.0  # state-sized arrays touched per stage update
-    ns, nb, nf = (6, 12, 6) if mhd else (4, 10, 4) if bq else (3, 6, 3)
+    ns, nb, nf = (6, 12, 6) if mhd else (4, 10, 4) if bq else (1, 1, 1) if gpe else (3, 6, 3)
     return {
         "zinv": (ns * sc + nb * sa) * esz,
         "yinv": (nb * sa + nb * sb) * esz,
@@ -188,6 +197,56 @@ def run_boussinesq(pst, torch, I, n=512, steps=10, warmup=2):
     return res
 
 
+def run_leg(plan, torch, kb, nstage, steps, warmup):
+    """Time `steps` steps of a prepared plan: ms per step and per pass."""
+    plan.step(warmup)
+    torch.cuda.synchronize()
+    plan.timers(reset=True)
+    ms, per = timed_steps(plan, torch, steps)
+    tm = plan.timers(reset=True)
+    kern = {k: {"ms": tm[k][0] / max(tm[k][1], 1), "launches": tm[k][1]} for k in KINDS}
+    for k in KINDS:
+        kern[k]["GB_s"] = kb[k] / kern[k]["ms"] / 1e6
+    return {"steps": steps, "ms_per_step": ms, "median_step_ms": float(np.median(per)), "kernels": kern,
+            "effective_GB_s": nstage * sum(kb.values()) / ms / 1e6, "energy_end": plan.energy()}
+
+
+def run_gpe(pst, torch, I, n=512, steps=10, warmup=2):
+    """Gross-Pitaevskii 512^3 FP32 RK4 (the paper's fourth solver, eq. gpe):
+    alpha = 0.5, beta = 1, dt = 1e-3, random-phase psi with E(k) ~ k^2
+    exp(-(k/3)^2), half the particles in the k = 0 condensate."""
+    plan = pst.Plan(n, solver="gpe", precision="fp32", rk_order=4, dt=1e-3, alpha=0.5, beta=1.0, timers=True)
+    psi = I.random_wavefunction((n, n, n), 1, condensate=0.5, kcut=24, dtype=np.complex64)
+    plan.set_state(psi[None])
+    del psi
+    res = run_leg(plan, torch, kernel_bytes(n, 8, 4, gpe=True), 4, steps, warmup)
+    res.update({"n": n, "precision": "fp32", "rk_order": 4, "alpha": 0.5, "beta": 1.0})
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+ANISO_SHAPE, ANISO_BOX = (1024, 1024, 256), (2 * np.pi, 2 * np.pi, np.pi / 2)
+
+
+def run_aniso(pst, torch, I, steps=5, warmup=1):
+    """Navier-Stokes on the paper's 4:4:1 grid 1024 x 1024 x 256 (box 2 pi x 2 pi
+    x pi/2, so the grid spacing is the same in every direction), FP32 RK4,
+    nu = 1e-3, dt = 2.5e-4: the 512^3 workload's spectrum (seed 1, unit
+    energy; the modes |a_i k_i| <= 24 carry it) and shell 2-3 forcing."""
+    plan = pst.Plan(0, precision="fp32", rk_order=4, nu=1e-3, dt=2.5e-4, timers=True, shape=ANISO_SHAPE,
+                    box=ANISO_BOX)
+    kc = (24, 24, 6)
+    plan.set_state(I.random_solenoidal(0, 1, kcut=kc, dtype=np.complex64, shape=ANISO_SHAPE, box=ANISO_BOX))
+    plan.set_forcing(I.forcing_shells(0, 1, dtype=np.complex64, shape=ANISO_SHAPE, box=ANISO_BOX))
+    res = run_leg(plan, torch, kernel_bytes(0, 8, 4, shape=ANISO_SHAPE), 4, steps, warmup)
+    res.update({"shape": list(ANISO_SHAPE), "box": [float(b) for b in ANISO_BOX], "precision": "fp32",
+                "rk_order": 4})
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
+
+
 def copy_bandwidth(torch, gib=4, reps=5):
     """A plain device-to-device copy of `gib` GiB: read + write bytes per second."""
     src = torch.empty(gib << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -204,6 +263,29 @@ def copy_bandwidth(torch, gib=4, reps=5):
     del src, dst
     torch.cuda.empty_cache()
     return 2.0 * (gib << 30) / ms / 1e6
+
+
+def mall_copy_bandwidth(torch, sizes_mb=(32, 64, 100, 128, 200), reps=50):
+    """Device copies whose source + destination (2x the size) stay within or
+    cross the 256 MB last-level cache (MALL): read + write bytes per second,
+    the practical ceiling of the ensemble's and the FNO's working sets."""
+    out = {}
+    for mb in sizes_mb:
+        src = torch.empty(mb << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        out[f"{mb}MB"] = 2.0 * (mb << 20) / (a.elapsed_time(b) / reps) / 1e6
+        del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_fft(pst, torch, n, prec, reps=5, nf=3):
@@ -259,11 +341,16 @@ def run_ensemble(pst, torch, I, steps=200, seq_steps=10):
         torch.cuda.synchronize()
         timings[mode] = (time.perf_counter() - t0) * 1e3 / nst
     pts = sum(n ** 3 for n in sizes)
+    # algorithmic pass traffic of one RK4 step of all runs (every run's five
+    # passes per stage, as for a single plan)
+    step_bytes = sum(4 * sum(kernel_bytes(n, 8, 4).values()) for n in sizes)
+    res["algorithmic_GB_per_step"] = step_bytes / 1e9
     res["ms_per_step"] = timings
     res["wall_s_200_steps_tuned"] = timings[tuned] * steps / 1e3
     res["point_steps_per_s"] = pts / (timings[tuned] / 1e3)
     res["speedup_vs_sequential"] = timings["sequential"] / timings[tuned]
     res["speedup_vs_batched"] = timings["batched"] / timings[tuned]
+    res["effective_GB_s_tuned"] = step_bytes / timings[tuned] / 1e6
     e = ens.energy()
     res["energy_range_end"] = [float(e.min()), float(e.max())]
     ens.close()
@@ -379,6 +466,7 @@ def main():
     n = a.n
     print("[bench] device copy bandwidth (4 GiB)", file=sys.stderr, flush=True)
     copy_gbs = copy_bandwidth(torch)
+    mall = mall_copy_bandwidth(torch)
     if a.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -387,7 +475,7 @@ def main():
         del src, dst
     print(f"[bench] n={n} fp32 solver: warmup {a.warmup}, timed {a.steps}", file=sys.stderr, flush=True)
     ms32, tm32, e32, info = run_solver(pst, torch, I, n, "fp32", a.steps, a.warmup)
-    out_extra = {"copy_GB_s": copy_gbs,
+    out_extra = {"copy_GB_s": copy_gbs, "mall_copy_GB_s": mall,
                  "fp32": {"ms_per_step": ms32, "median_step_ms": info["median_step_ms"], "energy_end": e32}}
     per32 = {k: tm32[k][0] / max(tm32[k][1], 1) for k in KINDS}
     kb32 = kernel_bytes(n, 8, 4)
@@ -424,10 +512,19 @@ def main():
     if not a.no_bq and n == 512:
         print("[bench] Boussinesq 512^3 FP32 RK4 (10 steps)", file=sys.stderr, flush=True)
         out_extra["boussinesq512"] = run_boussinesq(pst, torch, I)
+    if not a.no_gpe and n == 512:
+        print("[bench] Gross-Pitaevskii 512^3 FP32 RK4 (10 steps)", file=sys.stderr, flush=True)
+        out_extra["gpe512"] = run_gpe(pst, torch, I)
+    if not a.no_aniso:
+        print("[bench] Navier-Stokes 1024x1024x256 FP32 RK4 (5 steps)", file=sys.stderr, flush=True)
+        out_extra["aniso_1024x1024x256"] = run_aniso(pst, torch, I)
     if not a.no_fno:
         print("[bench] FNO surrogate forward / training step (64^3, batch 8)", file=sys.stderr, flush=True)
         out_extra["fno"] = run_fno(pst, torch, I)
-    out_extra["surrogate"] = surrogate_summary(a.surrogate)
+    if not a.no_surrogate:
+        print("[bench] surrogate pipeline: data, training, evaluation, hybrid rollout", file=sys.stderr,
+              flush=True)
+    out_extra["surrogate"] = surrogate_summary(not a.no_surrogate)
     # dominant kernel of the headline (FP32) step
     dom = max(KINDS, key=lambda k: tm32[k][0])
     ach = kb32[dom] / per32[dom] / 1e6

@@ -102,6 +102,14 @@ typedef struct {
     double nbv;       /* Brunt-Vaisala frequency N (Boussinesq; ignored otherwise) */
     double alpha;     /* GPE: coefficient of the Laplacian (hbar / 2m); ignored otherwise */
     double beta;      /* GPE: coupling of |psi|^2 psi (g / hbar); ignored otherwise */
+    /* Anisotropic grids (Sec. 2: the point counts N_i and box lengths L_i may
+     * differ per direction): points per direction (each a supported n; 0
+     * selects n) and box lengths (0 selects 2 pi).  Physical wavenumbers are
+     * 2 pi p / L_i, every axis has its own cutoff K_i, and layouts become
+     * physical [c][nz][ny][nx], spectral [c][nz][ny][nx/2+1] (GPE [c][nz][ny][nx]).
+     * SPHERE needs a cubic 2 pi grid; ensembles and the neural operator are cubic. */
+    int nx, ny, nz;
+    double lx, ly, lz;
 } pst_params;
 
 typedef struct {
@@ -112,6 +120,9 @@ typedef struct {
     int radices[4];           /* FFT radix schedule of the n-point transforms (0-terminated) */
     int tile_lines;           /* lines per workgroup in the strided passes */
     long long steps_done;     /* time steps taken since the last set_state */
+    int nx, ny, nz;           /* points per direction (n = nz) */
+    int kcut_x, kcut_y;       /* dealias cutoffs of x and y (kcut: z) */
+    int nshells;              /* shells a pst_spectrum call needs at least */
 } pst_info;
 
 /* Kernel kinds reported by pst_timer_read (PST_FLAG_TIMERS). */
@@ -143,8 +154,10 @@ const char *pst_last_error(const pst_plan *plan);
 int pst_supported_n(int n);
 
 /* Create a plan (Sec. 3.2, plan creation): validates p, allocates the state,
- * the pass buffers, FP64-generated twiddle and integrating-factor tables
- * (rounded once to the plan precision).  hip_stream (hipStream_t, may be NULL
+ * the pass buffers, and the twiddle and integrating-factor tables, generated
+ * in FP64 or better and rounded once to the plan precision (FP32 transforms
+ * evaluate their twiddles with the hardware sine and cosine instead of
+ * reading the table).  hip_stream (hipStream_t, may be NULL
  * for the null stream) is borrowed and must outlive the plan.  The state
  * starts at zero.  Errors: INVALID_ARG, UNSUPPORTED_N, UNSUPPORTED, OOM, HIP. */
 pst_status pst_plan_create(const pst_params *p, void *hip_stream, pst_plan **out);

@@ -412,14 +412,8 @@ extern "C" pst_status pst_ensemble_create(int nruns, const int* n, const pst_par
         kv.second = ci++;
         EnsClassHost h{};
         h.n = kv.first;
-        const int nn = h.n, K = (nn + 2) / 3 - 1, M = 2 * K + 1;
-        h.geo.n = nn;
-        h.geo.K = K;
-        h.geo.M = M;
-        h.geo.nxk = K + 1;
-        h.geo.sc = (int64_t)(K + 1) * M * M;
-        h.geo.sa = (int64_t)(K + 1) * M * nn;
-        h.geo.sb = (int64_t)(K + 1) * nn * nn;
+        const int nn = h.n, K = (nn + 2) / 3 - 1;
+        h.geo = make_geo(nn, nn, nn, K, K, K, 1.0, 1.0, 1.0, 0);
         E->cls.push_back(h);
     }
     E->run_class.resize(nruns);

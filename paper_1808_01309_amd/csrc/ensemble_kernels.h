@@ -78,7 +78,7 @@ inline void ens_units_v(const Geo& g, int64_t* upr) {
     using LC = EnsLineCfg<T, N, V>;
     upr[0] = line_units<LC, ENS_NT>(g);
     upr[1] = ytile_units<TC, ENS_NT>(g, 6);
-    upr[2] = xtile_units<TC, ENS_NT>();
+    upr[2] = xtile_units<TC, ENS_NT>(g);
     upr[3] = ytile_units<TC, ENS_NT>(g, 3);
     upr[4] = line_units<LC, ENS_NT>(g);
 }
@@ -108,9 +108,9 @@ __device__ __forceinline__ void ens_unit_v(const EnsClass<T>& c, int pass, int s
             const cx<T>* st = (stage_in_v ? c.V : c.U) + run * c.s_st;
             zinv_body<T, LC, ENS_NT, 1>(st, A, c.tw, g, lu, tid, sm);
         } break;
-        case 1: ypass_body<T, TC, ENS_NT, true>(A, B, c.tw, g, g.sa, g.sb, 6, lu, tid, sm); break;
+        case 1: ypass_body<T, TC, ENS_NT, true, TC::N>(A, B, c.tw, g, g.sa, g.sb, 6, lu, tid, sm); break;
         case 2: xpass_body<T, TC, ENS_NT, 0>(B, C, c.tw, g, lu, tid, sm); break;
-        case 3: ypass_body<T, TC, ENS_NT, false>(C, A, c.tw, g, g.sb, g.sa, 3, lu, tid, sm); break;
+        case 3: ypass_body<T, TC, ENS_NT, false, TC::N>(C, A, c.tw, g, g.sb, g.sa, 3, lu, tid, sm); break;
         default: {
             RkArgs<T> ra;
             ra.U = c.U + run * c.s_st;

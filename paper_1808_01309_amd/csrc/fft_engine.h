@@ -13,8 +13,12 @@
 // global memory; only the interior stages go through LDS.
 //
 // The forward transform uses sign -, the inverse sign +; neither scales.
-// Twiddles come from a table tw[m] = exp(-2 pi i m / N) generated in FP64 on
-// the host and rounded once to the element type.
+// FP64 twiddles come from a table tw[m] = exp(-2 pi i m / N) generated in
+// extended precision on the host and rounded once.  FP32 transforms (TWC)
+// evaluate theirs in registers with the hardware sine and cosine of the angle
+// in revolutions (m / N, exact in FP32): no table reads in the passes, at a
+// measured 1.3-1.4x the table's rounding error for one 512-point 3D transform
+// or right-hand side and the same error after 20 RK4 steps.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -87,6 +87,8 @@ using XCfg = KCfg<typename XPlan<T, N, MHD>::P, XPlan<T, N, MHD>::G, xpass_lines
 template <typename T, class CF, int NT> constexpr int line_lds() { return (NT / CF::G) * LineLds<T>::size(CF::N); }
 template <typename T, class CF, int NT> constexpr int tile_lds() { return (NT / (CF::G * CF::TL)) * CF::N * (CF::TL + 1); }
 template <int N, int TL> constexpr int ztiles() { return (N + TL - 1) / TL; }
+// z tiles of a plan's z axis (the strided passes transform y or x)
+template <int TL> __host__ __device__ inline int zt_count(const Geo& g) { return (g.n + TL - 1) / TL; }
 
 // Workgroups are dispatched to the 8 XCDs round-robin; xcd_unit renumbers
 // them so that each XCD works through one contiguous range of units (a
@@ -99,15 +101,15 @@ __device__ __forceinline__ int64_t xcd_unit() {
 // Work units: a line body handles NT / G lines per unit, a tile body
 // NT / (G TL) tiles per unit.
 template <class CF, int NT> inline int64_t line_units(const Geo& g) {
-    return ((int64_t)g.nxk * g.M + NT / CF::G - 1) / (NT / CF::G);
+    return ((int64_t)g.nxk * g.My + NT / CF::G - 1) / (NT / CF::G);
 }
 template <class CF, int NT> inline int64_t ytile_units(const Geo& g, int nf) {
     constexpr int SG = NT / (CF::G * CF::TL);
-    return ((int64_t)nf * g.nxk * ztiles<CF::N, CF::TL>() + SG - 1) / SG;
+    return ((int64_t)nf * g.nxk * zt_count<CF::TL>(g) + SG - 1) / SG;
 }
-template <class CF, int NT> inline int64_t xtile_units() {
+template <class CF, int NT> inline int64_t xtile_units(const Geo& g) {
     constexpr int SG = NT / (CF::G * CF::TL);
-    return ((int64_t)CF::N * ztiles<CF::N, CF::TL>() + SG - 1) / SG;
+    return ((int64_t)g.ny * zt_count<CF::TL>(g) + SG - 1) / SG;
 }
 
 template <typename T>
@@ -128,6 +130,10 @@ struct RkArgs {
     const cx<T>* Ec;
     const cx<T>* E2c;
     T beta;
+    // non-cubic grids (|k|^2 not an integer): the factors are evaluated per
+    // mode in FP64 from these (nu or eta / kappa; GPE: alpha in visc[0])
+    double visc[2];
+    double hd;
 };
 
 // ------------------------------------------------------------ zinv + curl
@@ -147,12 +153,13 @@ __device__ __forceinline__ void zinv_body(const cx<T>* __restrict__ st, cx<T>* _
     constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
     const int l = tid / G, g = tid % G;
     const int64_t line = unit * LPB + l;
-    const bool active = line < (int64_t)geo.nxk * geo.M;
-    const int kx = active ? (int)(line / geo.M) : 0;
-    const int jy = active ? (int)(line % geo.M) : 0;
-    const T fkx = T(kx), fky = T(k_of_j(jy, geo));
+    const bool active = line < (int64_t)geo.nxk * geo.My;
+    const int kx = active ? (int)(line / geo.My) : 0;
+    const int jy = active ? (int)(line % geo.My) : 0;
+    // physical wavenumbers a_i k_i
+    const T fkx = T(geo.ax) * T(kx), fky = T(geo.ay) * T(ky_of_j(jy, geo)), az = T(geo.az);
     const LineLds<T> lds{sm + l * LS};
-    const int64_t lin = (int64_t)kx * geo.M + jy;
+    const int64_t lin = (int64_t)kx * geo.My + jy;
     for (int grp = 0; grp < NGRP; ++grp) {
         const cx<T>* src = st + (int64_t)(grp * 3) * geo.sc + lin * geo.M;
         cx<T> u[3][E];
@@ -169,7 +176,7 @@ __device__ __forceinline__ void zinv_body(const cx<T>* __restrict__ st, cx<T>* _
             cx<T> w[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const T fkz = T(k_of_pos(F::first_pos(g, e), N));
+                const T fkz = az * T(k_of_pos(F::first_pos(g, e), N));
                 const cx<T> a = u[0][e], b = u[1][e], d = u[2][e];
                 if (c == 0) w[e] = mul_i(cx<T>{fky * d.x - fkz * b.x, fky * d.y - fkz * b.y});
                 else if (c == 1) w[e] = mul_i(cx<T>{fkz * a.x - fkx * d.x, fkz * a.y - fkx * d.y});
@@ -205,7 +212,7 @@ __device__ __forceinline__ void zinv_body(const cx<T>* __restrict__ st, cx<T>* _
             cx<T> w[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const T fk = c == 0 ? fkx : c == 1 ? fky : T(k_of_pos(F::first_pos(g, e), N));
+                const T fk = c == 0 ? fkx : c == 1 ? fky : az * T(k_of_pos(F::first_pos(g, e), N));
                 w[e] = mul_i(cscale(th[e], fk));
             }
             F::run(w, g, lds, tw);
@@ -235,13 +242,17 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_zinv(const cx<T>* __restrict__ s
 // Tile of TL consecutive z for one (field, kx).  INV: rows = kept ky (M) ->
 // all y (N); forward: all y -> kept ky.  A block of NT threads runs
 // NT / (G TL) tiles side by side.
-template <typename T, class CF, int NT, bool INV>
+// ZN: the z length when it equals the y length N (cubic grids: compile-time
+// strides), 0 for the runtime geo.n
+template <typename T, class CF, int NT, bool INV, int ZN = 0>
 __device__ __forceinline__ void ypass_body(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                            const cx<T>* __restrict__ tw, const Geo& geo, int64_t fs_in,
                                            int64_t fs_out, int nf, int64_t unit, int tid, cx<T>* sm) {
+    // N: y points (the transform); the tile's TL columns are consecutive z of nz
     constexpr int N = CF::N, G = CF::G, TL = CF::TL, TLP = TL + 1, TT = G * TL, SG = NT / TT;
     using F = Fft<T, typename CF::P, G, INV, false, false, sizeof(T) == 4>;
-    constexpr int E = F::E, NTZ = ztiles<N, TL>();
+    constexpr int E = F::E;
+    const int nz = ZN ? ZN : geo.n, NTZ = ZN ? ztiles<(ZN ? ZN : 1), TL>() : zt_count<TL>(geo);
     const int s = tid / TT, r = tid % TT;
     const int t = r % TL, g = r / TL;
     const int64_t tile = unit * SG + s;
@@ -250,36 +261,36 @@ __device__ __forceinline__ void ypass_body(const cx<T>* __restrict__ in, cx<T>* 
     const int64_t rest = valid ? tile / NTZ : 0;
     const int kx = (int)(rest % geo.nxk), f = (int)(rest / geo.nxk);
     const int z = zt * TL + t;
-    const bool zin = valid && z < N;
-    const int rows_in = INV ? geo.M : N, rows_out = INV ? N : geo.M;
-    const cx<T>* src = in + f * fs_in + (int64_t)kx * rows_in * N + z;
-    cx<T>* dst = out + f * fs_out + (int64_t)kx * rows_out * N + z;
+    const bool zin = valid && z < nz;
+    const int rows_in = INV ? geo.My : N, rows_out = INV ? N : geo.My;
+    const cx<T>* src = in + f * fs_in + (int64_t)kx * rows_in * nz + z;
+    cx<T>* dst = out + f * fs_out + (int64_t)kx * rows_out * nz + z;
     cx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int p = F::first_pos(g, e);
-        const int row = INV ? j_of_pos(p, geo) : p;
-        v[e] = (zin && row >= 0) ? src[(int64_t)row * N] : czero<T>();
+        const int row = INV ? jy_of_pos(p, geo) : p;
+        v[e] = (zin && row >= 0) ? src[(int64_t)row * nz] : czero<T>();
     }
     F::run(v, g, TileLds<T, TLP>{sm + s * N * TLP + t}, tw);
     if (zin) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int q = F::last_pos(g, e);
-            const int row = INV ? q : j_of_pos(q, geo);
-            if (row >= 0) dst[(int64_t)row * N] = v[e];
+            const int row = INV ? q : jy_of_pos(q, geo);
+            if (row >= 0) dst[(int64_t)row * nz] = v[e];
         }
     }
 }
 
-template <typename T, class CF, bool INV>
+template <typename T, class CF, bool INV, int ZN>
 __global__ __launch_bounds__((CF::G * CF::TL)) void k_ypass(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                           const cx<T>* __restrict__ tw, Geo geo, int64_t fs_in,
                                                           int64_t fs_out, int nf) {
     __shared__ cx<T> sm[tile_lds<T, CF, CF::G * CF::TL>()];
     // FP64: each XCD takes a contiguous range of tiles (measured 10% faster; FP32 slightly slower)
-    ypass_body<T, CF, CF::G * CF::TL, INV>(in, out, tw, geo, fs_in, fs_out, nf,
-                                           sizeof(T) == 8 ? xcd_unit() : (int64_t)blockIdx.x, threadIdx.x, sm);
+    ypass_body<T, CF, CF::G * CF::TL, INV, ZN>(in, out, tw, geo, fs_in, fs_out, nf,
+                                               sizeof(T) == 8 ? xcd_unit() : (int64_t)blockIdx.x, threadIdx.x, sm);
 }
 
 // ------------------------------------------------------------ fused x pass
@@ -296,18 +307,20 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     constexpr int N = CF::N, G = CF::G, TL = CF::TL, TLP = TL + 1, TT = G * TL, SG = NT / TT;
     using FI = Fft<T, typename CF::P, G, true, false, false, sizeof(T) == 4>;
     using FF = Fft<T, typename CF::P, G, false, true, false, sizeof(T) == 4>;
-    constexpr int E = FI::E, NTZ = ztiles<N, TL>();
+    // N: x points (the transform); tiles over y (ny) and z tiles of nz
+    constexpr int E = FI::E;
+    const int nz = geo.n, NTZ = zt_count<TL>(geo);
     constexpr int NP = MHD ? 6 : BQ ? 5 : 3;   // backward pairs
     constexpr int NO = MHD ? 3 : 2;            // forward packed lines
     constexpr int NOUT = MHD ? 6 : BQ ? 4 : 3; // output fields
     const int s = tid / TT, r = tid % TT;
     const int t = r % TL, g = r / TL;
     const int64_t tile = unit * SG + s;
-    const bool valid = tile < (int64_t)N * NTZ;
+    const bool valid = tile < (int64_t)geo.ny * NTZ;
     const int zt = valid ? (int)(tile % NTZ) : 0;
     const int y = valid ? (int)(tile / NTZ) : 0;
     const int z = zt * TL + t;
-    const bool zin = valid && z < N;
+    const bool zin = valid && z < nz;
     // PPB: two LDS buffers of the block's tiles, used by alternate phases
     // (staging of a pair, transform exchanges, output staging), so that each
     // phase needs a single barrier (see Fft::run_pp).  BLK: block-padded tile
@@ -322,9 +335,9 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     const TV lds{sm + s * TSZ1 + t};
     const TV lds1{sm + (PPB ? TSZ : 0) + s * TSZ1 + t};
     int ex = 0;   // LDS phases so far
-    const int64_t nn = (int64_t)N * N;
-    const int64_t off = (int64_t)y * N + z;
-    const int K = geo.K;
+    const int64_t nn = (int64_t)geo.ny * nz;   // stride of one kx plane
+    const int64_t off = (int64_t)y * nz + z;
+    const int K = geo.Kx;
     // Each kept row kx <= K of a pair (v, i k x v) is read from HBM once into
     // LDS (coalesced along z); the packed line Z = V + i W and its Hermitian
     // mirror Z(N - kx) = conj V + i conj W are then assembled from LDS.
@@ -335,19 +348,19 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     // current pair's LDS barrier and assembly, which hides their latency.
     constexpr int IT = (N / 2 - 1) / G + 1;
     cx<T> la[IT], lb[IT];
-    auto load_pair = [&](int pi) {
+    auto load_pair = [&](int pi, bool zin_, int64_t off_) {
         // pairs (v_c, (i k x v)_c); Boussinesq adds (theta_x, theta_y), (theta_z, theta)
         const int fu = (BQ && pi >= 3) ? 6 + 2 * (pi - 3) : (pi / 3) * 6 + pi % 3;
         const int fw = (BQ && pi >= 3) ? fu + 1 : fu + 3;
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             const int kx = g + i * G;
-            const bool ok = zin && kx <= K;
-            la[i] = ok ? Bf[fu * geo.sb + kx * nn + off] : czero<T>();
-            lb[i] = ok ? Bf[fw * geo.sb + kx * nn + off] : czero<T>();
+            const bool ok = zin_ && kx <= K;
+            la[i] = ok ? Bf[fu * geo.sb + kx * nn + off_] : czero<T>();
+            lb[i] = ok ? Bf[fw * geo.sb + kx * nn + off_] : czero<T>();
         }
     };
-    load_pair(0);
+    load_pair(0, zin, off);
 #pragma unroll
     for (int pi = 0; pi < NP; ++pi) {
         // this tile's LDS, points 0 .. 2K+1 < N of the tile view
@@ -365,30 +378,30 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
                 }
             }
         }
-        if (pi + 1 < NP) load_pair(pi + 1);
+        if (pi + 1 < NP) load_pair(pi + 1, zin, off);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int p = FI::first_pos(g, e);
             const bool lo = p <= K, hi = p >= N - K;
             // SPLIT: p = g + d with d = first_pos(0, e) a multiple of 8, so
-            // kk = g + d or N - g - d splits as at() needs
-            const int d = FI::first_pos(0, e), kk = lo ? p : N - p;
-            cx<T> Z = czero<T>();
-            if (lo || hi) {
-                cx<T> U, W;
-                if constexpr (SPLIT) {
-                    U = lo ? stage.at(g, d) : stage.at(N - g, -d);
-                    W = lo ? stage.at(K + 1 + g, d) : stage.at(K + 1 + N - g, -d);
-                } else {
-                    U = stage(kk);
-                    W = stage(K + 1 + kk);
-                }
-                if (p == 0) Z = {U.x, W.x};
-                else if (lo) Z = {U.x - W.y, U.y + W.x};
-                else Z = {U.x + W.y, W.x - U.y};
+            // kk = g + d or N - g - d splits as at() needs.  Branch-free: every
+            // lane reads a valid row (row 0 for the points between the kept
+            // bands) and the result is selected.
+            const bool in = lo || hi;
+            const int d = FI::first_pos(0, e), kk = !in ? 0 : lo ? p : N - p;
+            cx<T> U, W;
+            if constexpr (SPLIT) {
+                const int b0 = !in ? 0 : lo ? g : N - g, dd = !in ? 0 : lo ? d : -d;
+                U = stage.at(b0, dd);
+                W = stage.at(K + 1 + b0, dd);
+            } else {
+                U = stage(kk);
+                W = stage(K + 1 + kk);
             }
-            v[pi][e] = Z;
+            cx<T> Z = lo ? cx<T>{U.x - W.y, U.y + W.x} : cx<T>{U.x + W.y, W.x - U.y};
+            if (p == 0) Z = {U.x, W.x};
+            v[pi][e] = in ? Z : czero<T>();
         }
         if constexpr (!PPB) __syncthreads();
         ++ex;
@@ -446,11 +459,15 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
         __syncthreads();
         if (zin) {
             const int fa = 2 * po, fb = 2 * po + 1;
-            for (int kx = g, d = 0; kx <= K; kx += G, d += G) {
+            // rows kx = g + i G <= K (a fixed, predicated count)
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const int kx = g + i * G, d = i * G;
+                if (kx > K) continue;
                 cx<T> a, b;
                 if constexpr (SPLIT) {
                     a = lo.at(g, d);
-                    b = kx == 0 ? lo(0) : lo.at(N - g, -d);
+                    b = lo.at(kx == 0 ? 0 : N - g, kx == 0 ? 0 : -d);   // the mirror N - kx (0 for kx = 0)
                 } else {
                     a = lo(kx);
                     b = lo(kx == 0 ? 0 : N - kx);
@@ -509,7 +526,7 @@ __global__ __launch_bounds__((CF::G * CF::TL), (xpass_two_per_cu<T, CF::N, SYS>(
     if constexpr (PER == 1) {
         xpass_body<T, CF, CF::G * CF::TL, SYS, PPB, true>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm, nbv);
     } else {
-        const int64_t ntl = (int64_t)CF::N * ztiles<CF::N, CF::TL>();
+        const int64_t ntl = (int64_t)geo.ny * zt_count<CF::TL>(geo);
         const int64_t u0 = xcd_unit() * PER;
         const int64_t u1 = u0 + PER < ntl ? u0 + PER : ntl;
         for (int64_t u = u0; u < u1; ++u) {
@@ -575,12 +592,12 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
     constexpr int NF = MHD ? 6 : BQ ? 4 : 3;
     const int l = tid / G, g = tid % G;
     const int64_t line = unit * LPB + l;
-    const bool active = line < (int64_t)geo.nxk * geo.M;
-    const int kx = active ? (int)(line / geo.M) : 0;
-    const int jy = active ? (int)(line % geo.M) : 0;
-    const int iky = k_of_j(jy, geo);
+    const bool active = line < (int64_t)geo.nxk * geo.My;
+    const int kx = active ? (int)(line / geo.My) : 0;
+    const int jy = active ? (int)(line % geo.My) : 0;
+    const int iky = ky_of_j(jy, geo);
     const LineLds<T> lds{sm + l * LS};
-    const int64_t lin = (int64_t)kx * geo.M + jy;
+    const int64_t lin = (int64_t)kx * geo.My + jy;
     cx<T> v[NF][E];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -591,16 +608,18 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
 #pragma unroll
     for (int f = 0; f < NF; ++f) F::run(v[f], g, lds, tw);
     if (!active) return;
-    const T scale = T(1) / (T(N) * T(N) * T(N));
-    const T fkx = T(kx), fky = T(iky);
+    const T scale = T(1) / (T(geo.nx) * T(geo.ny) * T(N));
+    // physical wavenumbers a_i k_i (equal to the integers on the 2 pi box)
+    const T fkx = T(geo.ax) * T(kx), fky = T(geo.ay) * T(iky);
+    const double kxy2 = geo.ax * geo.ax * kx * kx + geo.ay * geo.ay * iky * iky;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int q = F::last_pos(g, e);
         const int j = j_of_pos(q, geo);
         if (j < 0) continue;
         const int ikz = k_of_pos(q, N);
-        const T fkz = T(ikz);
-        const int k2 = kx * kx + iky * iky + ikz * ikz;
+        const T fkz = T(geo.az) * T(ikz);
+        const int k2 = kx * kx + iky * iky + ikz * ikz;   // integer |k|^2: table index (2 pi box)
         const int64_t idx = lin * geo.M + j;
         cx<T> n0 = cscale(v[0][e], scale), n1 = cscale(v[1][e], scale), n2 = cscale(v[2][e], scale);
         // projection onto divergence-free fields: n - k (k . n) / |k|^2, zero at
@@ -610,7 +629,7 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
         if (k2 == 0 || cut) {
             o[0] = o[1] = o[2] = czero<T>();
         } else {
-            const T ik2 = T(1) / T(k2);
+            const T ik2 = T(1) / (fkx * fkx + fky * fky + fkz * fkz);
             const cx<T> kn = {(fkx * n0.x + fky * n1.x + fkz * n2.x) * ik2, (fkx * n0.y + fky * n1.y + fkz * n2.y) * ik2};
             o[0] = {n0.x - fkx * kn.x, n0.y - fkx * kn.y};
             o[1] = {n1.x - fky * kn.x, n1.y - fky * kn.y};
@@ -624,9 +643,30 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
             for (int c = 0; c < 3; ++c) o[c] = cadd(o[c], ra.F[c * fs + fi]);
         }
         if (ra.lin_only) o[0] = o[1] = o[2] = czero<T>();
-        // integrating factors by |k|^2, loaded once per mode for all components
-        // (the stage-array stores in between would otherwise force reloads)
-        const T Eu = ra.E[0][k2], E2u = ra.E2[0][k2];
+        // integrating factors: by integer |k|^2 from the tables (2 pi box) or,
+        // on other boxes, exp(-visc |k|^2 h / 2) evaluated here in FP64 and
+        // rounded once; loaded once per mode for all components (the
+        // stage-array stores in between would otherwise force reloads)
+        T Eu, E2u;
+        if (!geo.aniso) {
+            Eu = ra.E[0][k2];
+            E2u = ra.E2[0][k2];
+        } else {
+            const double eu = exp(-0.5 * ra.visc[0] * ra.hd * (kxy2 + geo.az * geo.az * ikz * ikz));
+            Eu = T(eu);
+            E2u = T(eu * eu);
+        }
+        // the second group's factors (b, theta), loaded where they are used
+        auto second_if = [&](T& Eb, T& E2b) {
+            if (!geo.aniso) {
+                Eb = ra.E[1][k2];
+                E2b = ra.E2[1][k2];
+            } else {
+                const double eb = exp(-0.5 * ra.visc[1] * ra.hd * (kxy2 + geo.az * geo.az * ikz * ikz));
+                Eb = T(eb);
+                E2b = T(eb * eb);
+            }
+        };
 #pragma unroll
         for (int c = 0; c < 3; ++c) rk_apply(mode, U, V, Acc, R, ra.h, c * geo.sc + idx, Eu, E2u, o[c]);
         if constexpr (MHD) {
@@ -637,7 +677,8 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
             b[1] = mul_i(cx<T>{fkz * m0.x - fkx * m2.x, fkz * m0.y - fkx * m2.y});
             b[2] = mul_i(cx<T>{fkx * m1.x - fky * m0.x, fkx * m1.y - fky * m0.y});
             if (ra.lin_only || cut) b[0] = b[1] = b[2] = czero<T>();
-            const T Eb = ra.E[1][k2], E2b = ra.E2[1][k2];
+            T Eb, E2b;
+            second_if(Eb, E2b);
 #pragma unroll
             for (int c = 0; c < 3; ++c) rk_apply(mode, U, V, Acc, R, ra.h, (3 + c) * geo.sc + idx, Eb, E2b, b[c]);
         }
@@ -645,7 +686,9 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
             // scalar: D (-F[u . grad theta] + N w_z), its own integrating factor
             cx<T> q = cscale(v[3][e], scale);
             if (ra.lin_only || cut) q = czero<T>();
-            rk_apply(mode, U, V, Acc, R, ra.h, 3 * geo.sc + idx, ra.E[1][k2], ra.E2[1][k2], q);
+            T Eb, E2b;
+            second_if(Eb, E2b);
+            rk_apply(mode, U, V, Acc, R, ra.h, 3 * geo.sc + idx, Eb, E2b, q);
         }
     }
 }
@@ -916,7 +959,7 @@ __device__ __forceinline__ void zinv_gpe_body(const cx<T>* __restrict__ st, cx<T
     constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
     const int l = tid / G, g = tid % G;
     const int64_t line = unit * LPB + l;
-    const bool active = line < (int64_t)geo.nxk * geo.M;
+    const bool active = line < (int64_t)geo.nxk * geo.My;
     const LineLds<T> lds{sm + l * LS};
     const cx<T>* src = st + (active ? line : 0) * geo.M;
     cx<T> v[E];
@@ -950,21 +993,22 @@ __device__ __forceinline__ void xpass_gpe_body(const cx<T>* __restrict__ Bf, cx<
     constexpr int N = CF::N, G = CF::G, TL = CF::TL, TT = G * TL, SG = NT / TT;
     using FI = Fft<T, typename CF::P, G, true, false, false, sizeof(T) == 4>;
     using FF = Fft<T, typename CF::P, G, false, true, false, sizeof(T) == 4>;
-    constexpr int E = FI::E, NTZ = ztiles<N, TL>();
+    constexpr int E = FI::E;
+    const int nz = geo.n, NTZ = zt_count<TL>(geo);
     const int s = tid / TT, r = tid % TT;
     const int t = r % TL, g = r / TL;
     const int64_t tile = unit * SG + s;
-    const bool valid = tile < (int64_t)N * NTZ;
+    const bool valid = tile < (int64_t)geo.ny * NTZ;
     const int zt = valid ? (int)(tile % NTZ) : 0;
     const int y = valid ? (int)(tile / NTZ) : 0;
     const int z = zt * TL + t;
-    const bool zin = valid && z < N;
+    const bool zin = valid && z < nz;
     const TileBlk<T, TL> lds{sm + s * TileBlk<T, TL>::size(N) + t};
-    const int64_t nn = (int64_t)N * N, off = (int64_t)y * N + z;
+    const int64_t nn = (int64_t)geo.ny * nz, off = (int64_t)y * nz + z;
     cx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int j = j_of_pos(FI::first_pos(g, e), geo);
+        const int j = jx_of_pos(FI::first_pos(g, e), geo);
         v[e] = (zin && j >= 0) ? Bf[j * nn + off] : czero<T>();
     }
     FI::run(v, g, lds, tw);
@@ -977,7 +1021,7 @@ __device__ __forceinline__ void xpass_gpe_body(const cx<T>* __restrict__ Bf, cx<
     if (zin) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int j = j_of_pos(FF::last_pos(g, e), geo);
+            const int j = jx_of_pos(FF::last_pos(g, e), geo);
             if (j >= 0) Cf[j * nn + off] = v[e];
         }
     }
@@ -1043,10 +1087,10 @@ __device__ __forceinline__ void zfwd_gpe_lines(const cx<T>* __restrict__ D, cons
     constexpr int E = F::E, LPB = NT / G, LS = LineLds<T>::size(N);
     const int l = tid / G, g = tid % G;
     const int64_t line = unit * LPB + l;
-    const bool active = line < (int64_t)geo.nxk * geo.M;
-    const int jx = active ? (int)(line / geo.M) : 0;
-    const int jy = active ? (int)(line % geo.M) : 0;
-    const int ikx = k_of_j(jx, geo), iky = k_of_j(jy, geo);
+    const bool active = line < (int64_t)geo.nxk * geo.My;
+    const int jx = active ? (int)(line / geo.My) : 0;
+    const int jy = active ? (int)(line % geo.My) : 0;
+    const int ikx = kx_of_j(jx, geo), iky = ky_of_j(jy, geo);
     const LineLds<T> lds{sm + l * LS};
     cx<T> v[E];
     const cx<T>* src = D + (active ? line : 0) * N;
@@ -1054,8 +1098,9 @@ __device__ __forceinline__ void zfwd_gpe_lines(const cx<T>* __restrict__ D, cons
     for (int e = 0; e < E; ++e) v[e] = active ? src[F::first_pos(g, e)] : czero<T>();
     F::run(v, g, lds, tw);
     if (!active) return;
-    // -i beta F[|psi|^2 psi] with the forward scale 1/n^3
-    const T sb = ra.beta / (T(N) * T(N) * T(N));
+    // -i beta F[|psi|^2 psi] with the forward scale 1/(nx ny nz)
+    const T sb = ra.beta / (T(geo.nx) * T(geo.ny) * T(N));
+    const double kxy2 = geo.ax * geo.ax * ikx * ikx + geo.ay * geo.ay * iky * iky;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int q = F::last_pos(g, e);
@@ -1065,7 +1110,19 @@ __device__ __forceinline__ void zfwd_gpe_lines(const cx<T>* __restrict__ D, cons
         const int k2 = ikx * ikx + iky * iky + ikz * ikz;
         cx<T> nk = {sb * v[e].y, -sb * v[e].x};
         if (ra.lin_only) nk = czero<T>();
-        rk_apply_cx(mode, U, V, Acc, R, ra.h, line * geo.M + j, ra.Ec[k2], ra.E2c[k2], nk);
+        cx<T> Ef, E2f;
+        if (!geo.aniso) {
+            Ef = ra.Ec[k2];
+            E2f = ra.E2c[k2];
+        } else {   // exp(-i alpha |k|^2 h / 2) in FP64, rounded once
+            const double a = ra.visc[0] * ra.hd * (kxy2 + geo.az * geo.az * ikz * ikz);
+            double sn, cs, sn2, cs2;
+            sincos(0.5 * a, &sn, &cs);
+            sincos(a, &sn2, &cs2);
+            Ef = {T(cs), T(-sn)};
+            E2f = {T(cs2), T(-sn2)};
+        }
+        rk_apply_cx(mode, U, V, Acc, R, ra.h, line * geo.M + j, Ef, E2f, nk);
     }
 }
 
@@ -1104,6 +1161,10 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 
 template <typename T, int N>
 struct Impl {
+    // the plan's table of N-th roots of unity (one per distinct axis length)
+    static const void* twid(const pst_plan* P) {
+        return P->geo.n == N ? P->tw : P->geo.ny == N ? P->twy : P->twx;
+    }
     using C = NCfg<N>;
     static constexpr int TL = tile_lines<T>();
     static constexpr int TB = C::G * TL;
@@ -1117,56 +1178,64 @@ struct Impl {
         const unsigned nb = (unsigned)line_units<LC, LINE_BLOCK>(g);
         if (P->p.solver == PST_GPE)
             hipLaunchKernelGGL((k_zinv_gpe<T, LC>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
-                               (cx<T>*)P->A, (const cx<T>*)P->tw, g);
+                               (cx<T>*)P->A, (const cx<T>*)twid(P), g);
         else if (P->p.solver == PST_MHD)
             hipLaunchKernelGGL((k_zinv<T, LC, 2, false>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
-                               (cx<T>*)P->A, (const cx<T>*)P->tw, g);
+                               (cx<T>*)P->A, (const cx<T>*)twid(P), g);
         else if (P->p.solver == PST_BOUSSINESQ)
             hipLaunchKernelGGL((k_zinv<T, LC, 1, true>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
-                               (cx<T>*)P->A, (const cx<T>*)P->tw, g);
+                               (cx<T>*)P->A, (const cx<T>*)twid(P), g);
         else
             hipLaunchKernelGGL((k_zinv<T, LC, 1, false>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)st,
-                               (cx<T>*)P->A, (const cx<T>*)P->tw, g);
+                               (cx<T>*)P->A, (const cx<T>*)twid(P), g);
     }
     static void yinv(pst_plan* P) {
         KTimer tm(P, PST_K_YINV);
         const Geo& g = P->geo;
         const unsigned nb = (unsigned)ytile_units<TC, TC::G * TC::TL>(g, P->nfin);
-        hipLaunchKernelGGL((k_ypass<T, TC, true>), dim3(nb), dim3(TC::G * TC::TL), 0, P->stream,
-                           (const cx<T>*)P->A, (cx<T>*)P->B, (const cx<T>*)P->tw, g, g.sa, g.sb, P->nfin);
+        if (g.n == N)   // cubic: compile-time z strides
+            hipLaunchKernelGGL((k_ypass<T, TC, true, N>), dim3(nb), dim3(TC::G * TC::TL), 0, P->stream,
+                               (const cx<T>*)P->A, (cx<T>*)P->B, (const cx<T>*)twid(P), g, g.sa, g.sb, P->nfin);
+        else
+            hipLaunchKernelGGL((k_ypass<T, TC, true, 0>), dim3(nb), dim3(TC::G * TC::TL), 0, P->stream,
+                               (const cx<T>*)P->A, (cx<T>*)P->B, (const cx<T>*)twid(P), g, g.sa, g.sb, P->nfin);
     }
     static void xpass(pst_plan* P) {
         KTimer tm(P, PST_K_XPASS);
         const Geo& g = P->geo;
         if (P->p.solver == PST_GPE) {
-            hipLaunchKernelGGL((k_xpass_gpe<T, TC>), dim3((unsigned)xtile_units<TC, TB>()), dim3(TB), 0, P->stream,
-                               (const cx<T>*)P->B, (cx<T>*)P->C, (const cx<T>*)P->tw, g);
+            hipLaunchKernelGGL((k_xpass_gpe<T, TC>), dim3((unsigned)xtile_units<TC, TB>(g)), dim3(TB), 0, P->stream,
+                               (const cx<T>*)P->B, (cx<T>*)P->C, (const cx<T>*)twid(P), g);
         } else if (P->p.solver == PST_MHD) {
             using XC = XCfg<T, N, true>;
-            hipLaunchKernelGGL((k_xpass<T, XC, 1>), dim3((unsigned)xtile_units<XC, XC::G * XC::TL>()),
+            hipLaunchKernelGGL((k_xpass<T, XC, 1>), dim3((unsigned)xtile_units<XC, XC::G * XC::TL>(g)),
                                dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
-                               (const cx<T>*)P->tw, g, T(0));
+                               (const cx<T>*)twid(P), g, T(0));
         } else if (P->p.solver == PST_BOUSSINESQ) {
             // five backward pairs: the MHD tile (half the lines) keeps them in registers
             using XC = XCfg<T, N, true>;
             constexpr int per = xpass_per<T, XC, 2>();
-            hipLaunchKernelGGL((k_xpass<T, XC, 2>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(), per)),
+            hipLaunchKernelGGL((k_xpass<T, XC, 2>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(g), per)),
                                dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
-                               (const cx<T>*)P->tw, g, (T)P->p.nbv);
+                               (const cx<T>*)twid(P), g, (T)P->p.nbv);
         } else {
             using XC = XCfg<T, N, false>;
             constexpr int per = xpass_per<T, XC, 0>();
-            hipLaunchKernelGGL((k_xpass<T, XC, 0>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(), per)),
+            hipLaunchKernelGGL((k_xpass<T, XC, 0>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(g), per)),
                                dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
-                               (const cx<T>*)P->tw, g, T(0));
+                               (const cx<T>*)twid(P), g, T(0));
         }
     }
     static void yfwd(pst_plan* P) {
         KTimer tm(P, PST_K_YFWD);
         const Geo& g = P->geo;
         const unsigned nb = (unsigned)ytile_units<TC, TC::G * TC::TL>(g, P->nfout);
-        hipLaunchKernelGGL((k_ypass<T, TC, false>), dim3(nb), dim3(TC::G * TC::TL), 0, P->stream,
-                           (const cx<T>*)P->C, (cx<T>*)P->A, (const cx<T>*)P->tw, g, g.sb, g.sa, P->nfout);
+        if (g.n == N)
+            hipLaunchKernelGGL((k_ypass<T, TC, false, N>), dim3(nb), dim3(TC::G * TC::TL), 0, P->stream,
+                               (const cx<T>*)P->C, (cx<T>*)P->A, (const cx<T>*)twid(P), g, g.sb, g.sa, P->nfout);
+        else
+            hipLaunchKernelGGL((k_ypass<T, TC, false, 0>), dim3(nb), dim3(TC::G * TC::TL), 0, P->stream,
+                               (const cx<T>*)P->C, (cx<T>*)P->A, (const cx<T>*)twid(P), g, g.sb, g.sa, P->nfout);
     }
     static void zfwd(pst_plan* P, int mode, void* rhs_out) {
         KTimer tm(P, PST_K_ZFWD);
@@ -1188,97 +1257,58 @@ struct Impl {
         ra.Ec = (const cx<T>*)P->Etab[0];
         ra.E2c = (const cx<T>*)P->E2tab[0];
         ra.beta = (T)P->p.beta;
+        ra.visc[0] = P->p.solver == PST_GPE ? P->p.alpha : P->p.nu;
+        ra.visc[1] = P->p.eta;
+        ra.hd = P->p.dt;
         const unsigned nb = (unsigned)line_units<LC, LINE_BLOCK>(g);
         if (P->p.solver == PST_GPE)
             hipLaunchKernelGGL((k_zfwd_gpe<T, LC>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
-                               (const cx<T>*)P->tw, g, ra, mode);
+                               (const cx<T>*)twid(P), g, ra, mode);
         else if (P->p.solver == PST_MHD)
             hipLaunchKernelGGL((k_zfwd<T, LC, 1>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
-                               (const cx<T>*)P->tw, g, ra, mode);
+                               (const cx<T>*)twid(P), g, ra, mode);
         else if (P->p.solver == PST_BOUSSINESQ)
             hipLaunchKernelGGL((k_zfwd<T, LC, 2>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
-                               (const cx<T>*)P->tw, g, ra, mode);
+                               (const cx<T>*)twid(P), g, ra, mode);
         else
             hipLaunchKernelGGL((k_zfwd<T, LC, 0>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
-                               (const cx<T>*)P->tw, g, ra, mode);
+                               (const cx<T>*)twid(P), g, ra, mode);
     }
-    static void fft_r2c(pst_plan* P, const void* in, void* out, int nf) {
-        const int64_t nxh = N / 2 + 1, plane = (int64_t)N * nxh;
-        const int64_t npairs = (int64_t)nf * N * N / 2;
-        {
-            KTimer tm(P, PST_K_FFTX);
-            hipLaunchKernelGGL((k_fftx_r2c<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
-                               P->stream, (const T*)in, (cx<T>*)out, (const cx<T>*)P->tw, npairs);
-        }
-        {
-            KTimer tm(P, PST_K_FFTY);
-            hipLaunchKernelGGL((k_fft_strided<T, N, false>), dim3(cdiv(nxh, TL), (unsigned)(nf * N)), dim3(TB), 0,
-                               P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, nxh, nxh, plane, T(1));
-        }
-        {
-            KTimer tm(P, PST_K_FFTZ);
-            const T s = T(1) / (T(N) * T(N) * T(N));
-            hipLaunchKernelGGL((k_fft_strided<T, N, false>), dim3(cdiv(plane, TL), (unsigned)nf), dim3(TB), 0,
-                               P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, plane, plane,
-                               (int64_t)N * plane, s);
-        }
+    // One axis of the standalone 3D transforms (the runtime composes x, y, z
+    // with each axis's own n).  x: nlines contiguous lines of N points (r2c /
+    // c2r pack two real lines per complex transform: nlines is even).
+    static void fftx_r2c(pst_plan* P, const void* in, void* out, int64_t nlines) {
+        KTimer tm(P, PST_K_FFTX);
+        const int64_t npairs = nlines / 2;
+        hipLaunchKernelGGL((k_fftx_r2c<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                           P->stream, (const T*)in, (cx<T>*)out, (const cx<T>*)twid(P), npairs);
     }
-    static void fft_c2r(pst_plan* P, const void* in, void* out, int nf, void* tmp) {
-        const int64_t nxh = N / 2 + 1, plane = (int64_t)N * nxh;
-        const int64_t npairs = (int64_t)nf * N * N / 2;
-        {
-            KTimer tm(P, PST_K_FFTZ);
-            hipLaunchKernelGGL((k_fft_strided<T, N, true>), dim3(cdiv(plane, TL), (unsigned)nf), dim3(TB), 0,
-                               P->stream, (const cx<T>*)in, (cx<T>*)tmp, (const cx<T>*)P->tw, plane, plane,
-                               (int64_t)N * plane, T(1));
-        }
-        {
-            KTimer tm(P, PST_K_FFTY);
-            hipLaunchKernelGGL((k_fft_strided<T, N, true>), dim3(cdiv(nxh, TL), (unsigned)(nf * N)), dim3(TB), 0,
-                               P->stream, (const cx<T>*)tmp, (cx<T>*)tmp, (const cx<T>*)P->tw, nxh, nxh, plane, T(1));
-        }
-        {
-            KTimer tm(P, PST_K_FFTX);
-            hipLaunchKernelGGL((k_fftx_c2r<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
-                               P->stream, (const cx<T>*)tmp, (T*)out, (const cx<T>*)P->tw, npairs);
-        }
+    static void fftx_c2r(pst_plan* P, const void* in, void* out, int64_t nlines) {
+        KTimer tm(P, PST_K_FFTX);
+        const int64_t npairs = nlines / 2;
+        hipLaunchKernelGGL((k_fftx_c2r<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                           P->stream, (const cx<T>*)in, (T*)out, (const cx<T>*)twid(P), npairs);
     }
-
-    static void fft_c2c(pst_plan* P, const void* in, void* out, int nf, int inverse) {
-        const int64_t plane = (int64_t)N * N;
-        const T s = inverse ? T(1) : T(1) / (T(N) * T(N) * T(N));
-        {
-            KTimer tm(P, PST_K_FFTX);
-            const int64_t nl = (int64_t)nf * plane;
-            if (inverse)
-                hipLaunchKernelGGL((k_fft_lines<T, N, true>), dim3(cdiv(nl, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
-                                   P->stream, (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)P->tw, nl, T(1));
-            else
-                hipLaunchKernelGGL((k_fft_lines<T, N, false>), dim3(cdiv(nl, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
-                                   P->stream, (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)P->tw, nl, T(1));
-        }
-        {
-            KTimer tm(P, PST_K_FFTY);
-            if (inverse)
-                hipLaunchKernelGGL((k_fft_strided<T, N, true>), dim3(cdiv(N, TL), (unsigned)(nf * N)), dim3(TB), 0,
-                                   P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, (int64_t)N,
-                                   (int64_t)N, plane, T(1));
-            else
-                hipLaunchKernelGGL((k_fft_strided<T, N, false>), dim3(cdiv(N, TL), (unsigned)(nf * N)), dim3(TB), 0,
-                                   P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, (int64_t)N,
-                                   (int64_t)N, plane, T(1));
-        }
-        {
-            KTimer tm(P, PST_K_FFTZ);
-            if (inverse)
-                hipLaunchKernelGGL((k_fft_strided<T, N, true>), dim3(cdiv(plane, TL), (unsigned)nf), dim3(TB), 0,
-                                   P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, plane, plane,
-                                   (int64_t)N * plane, s);
-            else
-                hipLaunchKernelGGL((k_fft_strided<T, N, false>), dim3(cdiv(plane, TL), (unsigned)nf), dim3(TB), 0,
-                                   P->stream, (const cx<T>*)out, (cx<T>*)out, (const cx<T>*)P->tw, plane, plane,
-                                   (int64_t)N * plane, s);
-        }
+    static void fftx_c2c(pst_plan* P, const void* in, void* out, int64_t nlines, int inverse) {
+        KTimer tm(P, PST_K_FFTX);
+        if (inverse)
+            hipLaunchKernelGGL((k_fft_lines<T, N, true>), dim3(cdiv(nlines, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                               P->stream, (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)twid(P), nlines, T(1));
+        else
+            hipLaunchKernelGGL((k_fft_lines<T, N, false>), dim3(cdiv(nlines, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
+                               P->stream, (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)twid(P), nlines, T(1));
+    }
+    // y or z: N-point complex transforms down columns of stride rs, ncols
+    // consecutive columns per plane, nplanes planes ps apart, times scale.
+    static void fft_cols(pst_plan* P, const void* in, void* out, int64_t rs, int64_t ncols, int64_t ps,
+                         int64_t nplanes, int inverse, double scale, int kind) {
+        KTimer tm(P, kind);
+        if (inverse)
+            hipLaunchKernelGGL((k_fft_strided<T, N, true>), dim3(cdiv(ncols, TL), (unsigned)nplanes), dim3(TB), 0,
+                               P->stream, (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)twid(P), rs, ncols, ps, T(scale));
+        else
+            hipLaunchKernelGGL((k_fft_strided<T, N, false>), dim3(cdiv(ncols, TL), (unsigned)nplanes), dim3(TB), 0,
+                               P->stream, (const cx<T>*)in, (cx<T>*)out, (const cx<T>*)twid(P), rs, ncols, ps, T(scale));
     }
 
     // Mode-pruned transforms.  Workspace `tmp`: t1 = nf N N m complex ([nf][z][y][kx < m],
@@ -1290,14 +1320,14 @@ struct Impl {
         {
             KTimer tm(P, PST_K_FFTY);
             hipLaunchKernelGGL((k_fft_cols_m<T, N, false, false, true>), dim3(cdiv(m, TL), (unsigned)(nf * N)),
-                               dim3(TB), 0, P->stream, t1, t2, (const cx<T>*)P->tw, (int64_t)m, (int64_t)m,
+                               dim3(TB), 0, P->stream, t1, t2, (const cx<T>*)twid(P), (int64_t)m, (int64_t)m,
                                (int64_t)N * m, (int64_t)m, m2 * m, m, T(1));
         }
         {
             KTimer tm(P, PST_K_FFTZ);
             const T s = T(1) / (T(N) * T(N) * T(N));
             hipLaunchKernelGGL((k_fft_cols_m<T, N, false, false, true>), dim3(cdiv(m2 * m, TL), (unsigned)nf),
-                               dim3(TB), 0, P->stream, t2, (cx<T>*)out, (const cx<T>*)P->tw, m2 * m, m2 * m,
+                               dim3(TB), 0, P->stream, t2, (cx<T>*)out, (const cx<T>*)twid(P), m2 * m, m2 * m,
                                (int64_t)N * m2 * m, m2 * m, m2 * m2 * m, m, s);
         }
     }
@@ -1308,13 +1338,13 @@ struct Impl {
         {
             KTimer tm(P, PST_K_FFTZ);
             hipLaunchKernelGGL((k_fft_cols_m<T, N, true, true, false>), dim3(cdiv(m2 * m, TL), (unsigned)nf),
-                               dim3(TB), 0, P->stream, (const cx<T>*)in, t2, (const cx<T>*)P->tw, m2 * m, m2 * m,
+                               dim3(TB), 0, P->stream, (const cx<T>*)in, t2, (const cx<T>*)twid(P), m2 * m, m2 * m,
                                m2 * m2 * m, m2 * m, (int64_t)N * m2 * m, m, T(1));
         }
         {
             KTimer tm(P, PST_K_FFTY);
             hipLaunchKernelGGL((k_fft_cols_m<T, N, true, true, false>), dim3(cdiv(m, TL), (unsigned)(nf * N)),
-                               dim3(TB), 0, P->stream, t2, t1, (const cx<T>*)P->tw, (int64_t)m, (int64_t)m, m2 * m,
+                               dim3(TB), 0, P->stream, t2, t1, (const cx<T>*)twid(P), (int64_t)m, (int64_t)m, m2 * m,
                                (int64_t)m, (int64_t)N * m, m, T(1));
         }
     }
@@ -1323,7 +1353,7 @@ struct Impl {
         {
             KTimer tm(P, PST_K_FFTX);
             hipLaunchKernelGGL((k_fftx_r2c_m<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
-                               P->stream, (const T*)in, (cx<T>*)tmp, (const cx<T>*)P->tw, npairs, m);
+                               P->stream, (const T*)in, (cx<T>*)tmp, (const cx<T>*)twid(P), npairs, m);
         }
         modes_yz_fwd(P, out, nf, m, tmp);
     }
@@ -1333,7 +1363,7 @@ struct Impl {
         {
             KTimer tm(P, PST_K_FFTX);
             hipLaunchKernelGGL((k_fftx_c2r_m<T, N>), dim3(cdiv(npairs, LINE_BLOCK / C::G)), dim3(LINE_BLOCK), 0,
-                               P->stream, (const cx<T>*)tmp, (T*)out, (const cx<T>*)P->tw, npairs, m);
+                               P->stream, (const cx<T>*)tmp, (T*)out, (const cx<T>*)twid(P), npairs, m);
         }
     }
 
@@ -1348,9 +1378,10 @@ struct Impl {
             l.xpass = &xpass;
             l.yfwd = &yfwd;
             l.zfwd = &zfwd;
-            l.fft_r2c = &fft_r2c;
-            l.fft_c2r = &fft_c2r;
-            l.fft_c2c = &fft_c2c;
+            l.fftx_r2c = &fftx_r2c;
+            l.fftx_c2r = &fftx_c2r;
+            l.fftx_c2c = &fftx_c2c;
+            l.fft_cols = &fft_cols;
             l.fft_r2c_modes = &fft_r2c_modes;
             l.fft_c2r_modes = &fft_c2r_modes;
             l.modes_yz_fwd = &modes_yz_fwd;

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <algorithm>
 #include <string>
 
 #include "fft_engine.h"
@@ -88,6 +89,8 @@ extern "C" int pst_supported_n(int n) {
     }
 }
 
+static void fft3_c2r(pst_plan* P, const void* in, void* out, int nf, void* tmp);
+
 // --------------------------------------------------------------- c2r without allocation
 // Device memory of pst_fft_c2r_noalloc: the n roots of unity followed by the
 // workspace of the z and y passes.  One copy per GPU, held until the process
@@ -164,14 +167,16 @@ extern "C" pst_status pst_fft_c2r_noalloc(int n, int precision, const void* in, 
     Q.p.precision = precision;
     Q.p.flags = 0;
     Q.stream = (hipStream_t)hip_stream;
-    Q.tw = base;
+    Q.geo = make_geo(n, n, n, 0, 0, 0, 1.0, 1.0, 1.0, 0);
+    Q.L = Q.Lx = Q.Ly = L;
+    Q.tw = Q.twx = Q.twy = base;
     Q.esz = es;
     if (precision == PST_FP64)
         hipLaunchKernelGGL(k_roots<double>, dim3((n + 255) / 256), dim3(256), 0, Q.stream, (cx<double>*)base, n);
     else
         hipLaunchKernelGGL(k_roots<float>, dim3((n + 255) / 256), dim3(256), 0, Q.stream, (cx<float>*)base, n);
     // every element of the workspace is written by the z pass before it is read
-    L->fft_c2r(&Q, in, out, nfields, tmp);
+    fft3_c2r(&Q, in, out, nfields, tmp);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(nullptr, PST_ERR_HIP, "fft_c2r_noalloc: kernel launch failed: %s", hipGetErrorString(e));
     return PST_OK;
@@ -212,29 +217,31 @@ static void drain_timers(pst_plan* P) {
 }
 
 // --------------------------------------------------------------- small kernels
+// ABI spectral layout [c][nz][ny][nxh] (nxh = nx/2 + 1, or nx for a complex
+// field) <-> compact kept modes [c][jx][jy][jz].
 template <typename T>
 __global__ void k_gather(const cx<T>* __restrict__ abi, cx<T>* __restrict__ st, Geo g, int ncomp) {
     const int64_t total = (int64_t)ncomp * g.sc;
-    const int nxh = g.full ? g.n : g.n / 2 + 1;
+    const int nx = g.nx, ny = g.ny, nz = g.n, nxh = g.full ? nx : nx / 2 + 1;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(i / g.sc);
         int64_t r = i % g.sc;
         const int jz = (int)(r % g.M);
         r /= g.M;
-        const int jy = (int)(r % g.M);
-        const int jx = (int)(r / g.M);
-        const int ky = k_of_j(jy, g), kz = k_of_j(jz, g);
-        const int iy = (ky + g.n) % g.n, iz = (kz + g.n) % g.n;
+        const int jy = (int)(r % g.My);
+        const int jx = (int)(r / g.My);
+        const int ky = ky_of_j(jy, g), kz = k_of_j(jz, g);
+        const int iy = (ky + ny) % ny, iz = (kz + nz) % nz;
+        const cx<T>* a = abi + (int64_t)c * nz * ny * nxh;
         if (g.full) {   // whole spectrum, no symmetry: a plain copy of the kept modes
-            const int ix = (k_of_j(jx, g) + g.n) % g.n;
-            st[i] = abi[(int64_t)c * g.n * g.n * g.n + ((int64_t)iz * g.n + iy) * g.n + ix];
+            const int ix = (kx_of_j(jx, g) + nx) % nx;
+            st[i] = a[((int64_t)iz * ny + iy) * nxh + ix];
             continue;
         }
         const int kx = jx;
-        const cx<T>* a = abi + (int64_t)c * g.n * g.n * nxh;
-        cx<T> v = a[((int64_t)iz * g.n + iy) * nxh + kx];
+        cx<T> v = a[((int64_t)iz * ny + iy) * nxh + kx];
         if (kx == 0) {
-            const cx<T> m = a[((int64_t)((g.n - iz) % g.n) * g.n + (g.n - iy) % g.n) * nxh];
+            const cx<T> m = a[((int64_t)((nz - iz) % nz) * ny + (ny - iy) % ny) * nxh];
             v = {T(0.5) * (v.x + m.x), T(0.5) * (v.y - m.y)};
         }
         st[i] = v;
@@ -243,22 +250,22 @@ __global__ void k_gather(const cx<T>* __restrict__ abi, cx<T>* __restrict__ st, 
 
 template <typename T>
 __global__ void k_scatter(const cx<T>* __restrict__ st, cx<T>* __restrict__ abi, Geo g, int ncomp) {
-    const int nxh = g.full ? g.n : g.n / 2 + 1;
-    const int64_t per = (int64_t)g.n * g.n * nxh, total = (int64_t)ncomp * per;
+    const int nx = g.nx, ny = g.ny, nz = g.n, nxh = g.full ? nx : nx / 2 + 1;
+    const int64_t per = (int64_t)nz * ny * nxh, total = (int64_t)ncomp * per;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(i / per);
         int64_t r = i % per;
         const int ix = (int)(r % nxh);
         r /= nxh;
-        const int iy = (int)(r % g.n), iz = (int)(r / g.n);
-        const int ky = k_of_pos(iy, g.n), kz = k_of_pos(iz, g.n);
+        const int iy = (int)(r % ny), iz = (int)(r / ny);
+        const int ky = k_of_pos(iy, ny), kz = k_of_pos(iz, nz);
         // full axis: signed kx, compact jx as for ky and kz
-        const int kx = g.full ? k_of_pos(ix, g.n) : ix;
-        const int jx = g.full ? (kx >= 0 ? kx : kx + g.M) : kx;
+        const int kx = g.full ? k_of_pos(ix, nx) : ix;
+        const int jx = g.full ? (kx >= 0 ? kx : kx + 2 * g.Kx + 1) : kx;
         cx<T> v = {T(0), T(0)};
-        if (kx <= g.K && -kx <= g.K && ky <= g.K && -ky <= g.K && kz <= g.K && -kz <= g.K) {
-            const int jy = ky >= 0 ? ky : ky + g.M, jz = kz >= 0 ? kz : kz + g.M;
-            v = st[(int64_t)c * g.sc + ((int64_t)jx * g.M + jy) * g.M + jz];
+        if (kx <= g.Kx && -kx <= g.Kx && ky <= g.Ky && -ky <= g.Ky && kz <= g.K && -kz <= g.K) {
+            const int jy = ky >= 0 ? ky : ky + g.My, jz = kz >= 0 ? kz : kz + g.M;
+            v = st[(int64_t)c * g.sc + ((int64_t)jx * g.My + jy) * g.M + jz];
         }
         abi[i] = v;
     }
@@ -275,13 +282,14 @@ __global__ __launch_bounds__(RED_THREADS) void k_energy_part(const cx<T>* __rest
     double acc = 0.0;
     const int64_t per = g.sc;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (int64_t)gridDim.x * blockDim.x) {
-        const int jx = (int)(i / ((int64_t)g.M * g.M));
+        const int jx = (int)(i / ((int64_t)g.My * g.M));
         // half spectrum: weight 2 off the kx = 0 plane; the full spectrum counts each mode once
-        const int kx = g.full ? k_of_j(jx, g) : jx;
+        const int kx = kx_of_j(jx, g);
         double w = (g.full || kx == 0) ? 1.0 : 2.0;
-        if (k2w) {  // enstrophy: weight |k|^2
-            const int ky = k_of_j((int)((i / g.M) % g.M), g), kz = k_of_j((int)(i % g.M), g);
-            w *= (double)(kx * kx + ky * ky + kz * kz);
+        if (k2w) {  // enstrophy: weight |k|^2 (physical wavenumbers)
+            const int ky = ky_of_j((int)((i / g.M) % g.My), g), kz = k_of_j((int)(i % g.M), g);
+            const double fx = g.ax * kx, fy = g.ay * ky, fz = g.az * kz;
+            w *= fx * fx + fy * fy + fz * fz;
         }
         double s = 0.0;
         for (int c = 0; c < nc; ++c) {
@@ -315,35 +323,36 @@ __global__ __launch_bounds__(RED_THREADS) void k_sum_final(const double* __restr
 
 constexpr int MAX_SHELLS = 2048;
 
-__device__ __forceinline__ int shell_of(long k2) { return (int)floor(sqrt((double)k2) + 0.5); }
+// shell of a mode: floor(|k| / dk + 1/2), dk the smallest a_i
+__device__ __forceinline__ int shell_of(double k2, double dk) { return (int)floor(sqrt(k2) / dk + 0.5); }
 
 // Shell spectrum with a fixed summation order (bitwise repeatable): block s
 // owns shell s.  Its threads stride over the (kx, ky) lines; along a line the
 // shell index grows with |kz|, so the line's modes in shell s are the |kz| of
-// one contiguous range, found from an estimate and the exact test
-// floor(|k| + 1/2) = s.  Per-thread sums are then combined by a fixed tree.
+// one contiguous range, found from an estimate and the exact test on
+// floor(|k| / dk + 1/2).  Per-thread sums are then combined by a fixed tree.
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_spectrum(const cx<T>* __restrict__ st, Geo g, int c0, int nc,
-                                                          double* __restrict__ bins) {
+                                                          double* __restrict__ bins, double dk) {
     __shared__ double sh[RED_THREADS];
     const int s = blockIdx.x;
-    const double hi = (s + 0.5) * (s + 0.5);
-    const int64_t per = g.sc, nlines = (int64_t)g.nxk * g.M;
+    const double hi = (s + 0.5) * dk * ((s + 0.5) * dk);
+    const int64_t per = g.sc, nlines = (int64_t)g.nxk * g.My;
     double acc = 0.0;
     for (int64_t l = threadIdx.x; l < nlines; l += RED_THREADS) {
-        const int jx = (int)(l / g.M), jy = (int)(l % g.M);
-        const int kx = g.full ? k_of_j(jx, g) : jx;
-        const int ky = k_of_j(jy, g);
-        const long r2 = (long)kx * kx + (long)ky * ky;
-        if ((double)r2 > hi) continue;   // every mode of the line lies beyond shell s
-        const double lo2 = (s - 0.5) * (s - 0.5) - (double)r2;
-        int a = lo2 > 0.0 ? (int)sqrt(lo2) : 0;
+        const int jx = (int)(l / g.My), jy = (int)(l % g.My);
+        const int kx = kx_of_j(jx, g), ky = ky_of_j(jy, g);
+        const double fx = g.ax * kx, fy = g.ay * ky;
+        const double r2 = fx * fx + fy * fy;
+        if (r2 > hi) continue;   // every mode of the line lies beyond shell s
+        const double lo2 = (s - 0.5) * dk * ((s - 0.5) * dk) - r2;
+        int a = lo2 > 0.0 ? (int)(sqrt(lo2) / g.az) : 0;
         a = a > 0 ? a - 1 : 0;
-        while (a <= g.K && shell_of(r2 + (long)a * a) < s) ++a;
+        while (a <= g.K && shell_of(r2 + (g.az * a) * (g.az * a), dk) < s) ++a;
         // half spectrum: 1/2 w |v|^2 (energy); full spectrum: |psi|^2 (number)
         const double w = g.full ? 1.0 : 0.5 * (kx == 0 ? 1.0 : 2.0);
         const int64_t line = l * g.M;
-        for (int kz = a; kz <= g.K && shell_of(r2 + (long)kz * kz) == s; ++kz) {
+        for (int kz = a; kz <= g.K && shell_of(r2 + (g.az * kz) * (g.az * kz), dk) == s; ++kz) {
             for (int sgn = 0; sgn < (kz == 0 ? 1 : 2); ++sgn) {
                 const int jz = sgn == 0 ? kz : g.M - kz;
                 double q = 0.0;
@@ -386,8 +395,36 @@ static pst_status dalloc(pst_plan* P, void** ptr, size_t bytes) {
 }
 
 static size_t abi_spec_bytes(const pst_plan* P, int ncomp) {
-    const size_t n = (size_t)P->p.n;
-    return (size_t)ncomp * n * n * (P->geo.full ? n : n / 2 + 1) * P->esz;
+    const size_t nx = (size_t)P->geo.nx;
+    return (size_t)ncomp * P->geo.n * P->geo.ny * (P->geo.full ? nx : nx / 2 + 1) * P->esz;
+}
+static size_t phys_points(const pst_plan* P) { return (size_t)P->geo.nx * P->geo.ny * P->geo.n; }
+
+// Standalone 3D transforms composed from one pass per axis (each axis with its
+// own n).  Physical [nf][nz][ny][nx], spectral [nf][nz][ny][nxh].
+static void fft3_r2c(pst_plan* P, const void* in, void* out, int nf) {
+    const Geo& g = P->geo;
+    const int64_t nxh = g.nx / 2 + 1, plane = (int64_t)g.ny * nxh;
+    P->Lx->fftx_r2c(P, in, out, (int64_t)nf * g.ny * g.n);
+    P->Ly->fft_cols(P, out, out, nxh, nxh, plane, (int64_t)nf * g.n, 0, 1.0, PST_K_FFTY);
+    P->L->fft_cols(P, out, out, plane, plane, plane * g.n, nf, 0, 1.0 / ((double)g.nx * g.ny * g.n), PST_K_FFTZ);
+}
+// c2r: in is left unchanged (the z and y passes work in tmp)
+static void fft3_c2r(pst_plan* P, const void* in, void* out, int nf, void* tmp) {
+    const Geo& g = P->geo;
+    const int64_t nxh = g.nx / 2 + 1, plane = (int64_t)g.ny * nxh;
+    P->L->fft_cols(P, in, tmp, plane, plane, plane * g.n, nf, 1, 1.0, PST_K_FFTZ);
+    P->Ly->fft_cols(P, tmp, tmp, nxh, nxh, plane, (int64_t)nf * g.n, 1, 1.0, PST_K_FFTY);
+    P->Lx->fftx_c2r(P, tmp, out, (int64_t)nf * g.ny * g.n);
+}
+// complex field: forward (sign -, 1 / (nx ny nz)) or inverse (sign +, unscaled)
+static void fft3_c2c(pst_plan* P, const void* in, void* out, int nf, int inverse) {
+    const Geo& g = P->geo;
+    const int64_t plane = (int64_t)g.ny * g.nx;
+    const double s = inverse ? 1.0 : 1.0 / ((double)g.nx * g.ny * g.n);
+    P->Lx->fftx_c2c(P, in, out, (int64_t)nf * g.ny * g.n, inverse);
+    P->Ly->fft_cols(P, out, out, g.nx, g.nx, plane, (int64_t)nf * g.n, inverse, 1.0, PST_K_FFTY);
+    P->L->fft_cols(P, out, out, plane, plane, plane * g.n, nf, inverse, s, PST_K_FFTZ);
 }
 
 static pst_status ensure_abi(pst_plan* P, size_t bytes) {
@@ -406,8 +443,7 @@ static pst_status ensure_abi(pst_plan* P, size_t bytes) {
 
 // host tables in FP64, rounded once to the plan precision
 template <typename T>
-static pst_status upload_tables(pst_plan* P) {
-    const int n = P->p.n, K = P->geo.K;
+static pst_status upload_roots(pst_plan* P, void* dst, int n) {
     std::vector<cx<T>> tw(n);
     for (int m = 0; m < n; ++m) {
         // exp(-2 pi i m / n) evaluated in extended precision, rounded once
@@ -415,7 +451,20 @@ static pst_status upload_tables(pst_plan* P) {
         tw[m].x = (T)cosl(a);
         tw[m].y = (T)(-sinl(a));
     }
-    HIPCHK(P, hipMemcpy(P->tw, tw.data(), sizeof(cx<T>) * n, hipMemcpyHostToDevice));
+    HIPCHK(P, hipMemcpy(dst, tw.data(), sizeof(cx<T>) * n, hipMemcpyHostToDevice));
+    return PST_OK;
+}
+
+template <typename T>
+static pst_status upload_tables(pst_plan* P) {
+    const int n = P->p.n;
+    // integer |k|^2 indexes the integrating factors on the 2 pi box; other
+    // boxes evaluate them per mode (the tables stay unused there)
+    const int K = std::max(P->geo.K, std::max(P->geo.Kx, P->geo.Ky));
+    pst_status s = upload_roots<T>(P, P->tw, n);
+    if (!s && P->twy != P->tw) s = upload_roots<T>(P, P->twy, P->geo.ny);
+    if (!s && P->twx != P->tw && P->twx != P->twy) s = upload_roots<T>(P, P->twx, P->geo.nx);
+    if (s) return s;
     const int nk2 = 3 * K * K + 1;
     if (P->p.solver == PST_GPE) {
         // exp(-i alpha |k|^2 h / 2) and its square, by integer |k|^2
@@ -444,6 +493,17 @@ static pst_status upload_tables(pst_plan* P) {
 }
 
 // --------------------------------------------------------------- plan
+static constexpr double TWO_PI = 6.28318530717958647692528676655900577;
+// points and box length of axis a (0 = x, 1 = y, 2 = z); 0 selects n and 2 pi
+static int ax_n(const pst_params* p, int a) {
+    const int m = a == 0 ? p->nx : a == 1 ? p->ny : p->nz;
+    return m > 0 ? m : p->n;
+}
+static double ax_len(const pst_params* p, int a) {
+    const double l = a == 0 ? p->lx : a == 1 ? p->ly : p->lz;
+    return l > 0.0 ? l : TWO_PI;
+}
+
 extern "C" void pst_plan_destroy(pst_plan* P) {
     if (!P) return;
     hipStreamSynchronize(P->stream);
@@ -451,6 +511,8 @@ extern "C" void pst_plan_destroy(pst_plan* P) {
                     P->E2tab[0], P->E2tab[1], P->force, P->abi, P->red};
     for (void* b : bufs)
         if (b) hipFree(b);
+    if (P->twy && P->twy != P->tw) hipFree(P->twy);
+    if (P->twx && P->twx != P->tw && P->twx != P->twy) hipFree(P->twx);
     for (auto& r : P->pending) {
         hipEventDestroy(r.a);
         hipEventDestroy(r.b);
@@ -484,29 +546,44 @@ extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst
         return fail(nullptr, PST_ERR_UNSUPPORTED, "dealias %d", p->dealias);
     if (p->flags & ~(unsigned)(PST_FLAG_LINEAR_ONLY | PST_FLAG_TIMERS))
         return fail(nullptr, PST_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
-    if (!pst_supported_n(p->n)) return fail(nullptr, PST_ERR_UNSUPPORTED_N, "n = %d not supported", p->n);
-    const Launchers* L = launchers_for(p->n, p->precision);
-    if (!L) return fail(nullptr, PST_ERR_UNSUPPORTED_N, "n = %d has no kernels", p->n);
+    for (int a = 0; a < 3; ++a) {
+        const int m = a == 0 ? p->nx : a == 1 ? p->ny : p->nz;
+        const double l = a == 0 ? p->lx : a == 1 ? p->ly : p->lz;
+        if (m < 0) return fail(nullptr, PST_ERR_INVALID_ARG, "axis %d: %d points", a, m);
+        if (!(l >= 0.0) || !isfinite(l)) return fail(nullptr, PST_ERR_INVALID_ARG, "axis %d: box length %g", a, l);
+        if (m == 0 && p->n == 0) return fail(nullptr, PST_ERR_UNSUPPORTED_N, "n = 0 not supported");
+        if (!pst_supported_n(ax_n(p, a)))
+            return fail(nullptr, PST_ERR_UNSUPPORTED_N, "axis %d: n = %d not supported", a, ax_n(p, a));
+    }
+    const bool cubic = ax_n(p, 0) == ax_n(p, 2) && ax_n(p, 1) == ax_n(p, 2) && ax_len(p, 0) == TWO_PI &&
+                       ax_len(p, 1) == TWO_PI && ax_len(p, 2) == TWO_PI;
+    if (!cubic && p->dealias == PST_DEALIAS_SPHERE)
+        return fail(nullptr, PST_ERR_UNSUPPORTED, "spherical truncation needs a cubic 2 pi grid");
+    const Launchers* L = launchers_for(ax_n(p, 2), p->precision);
+    const Launchers* Lx = launchers_for(ax_n(p, 0), p->precision);
+    const Launchers* Ly = launchers_for(ax_n(p, 1), p->precision);
+    if (!L || !Lx || !Ly) return fail(nullptr, PST_ERR_UNSUPPORTED_N, "no kernels for this grid");
 
     pst_plan* P = new pst_plan();
     P->p = *p;
     if (P->p.solver == PST_NS) P->p.eta = P->p.nu;
     P->stream = (hipStream_t)hip_stream;
     P->L = L;
+    P->Lx = Lx;
+    P->Ly = Ly;
     P->esz = p->precision == PST_FP64 ? 16 : 8;
-    // 2/3 rule: the largest K with 3K < n; NONE keeps every mode but the Nyquist;
-    // GPE (cubic product): the largest K with 4K < n, kx on the full axis
-    const int n = p->n;
-    const int K = gpe ? (n + 3) / 4 - 1 : p->dealias == PST_DEALIAS_NONE ? n / 2 - 1 : (n + 2) / 3 - 1;
-    const int M = 2 * K + 1;
-    P->geo.n = n;
-    P->geo.K = K;
-    P->geo.M = M;
-    P->geo.full = gpe ? 1 : 0;
-    P->geo.nxk = gpe ? M : K + 1;
-    P->geo.sc = (int64_t)P->geo.nxk * M * M;
-    P->geo.sa = (int64_t)P->geo.nxk * M * n;
-    P->geo.sb = (int64_t)P->geo.nxk * n * n;
+    // per-axis cutoffs.  2/3 rule: the largest K with 3K < n; NONE keeps every
+    // mode but the Nyquist; GPE (cubic product): the largest K with 4K < n, kx
+    // on the full axis
+    auto cut = [&](int m) {
+        return gpe ? (m + 3) / 4 - 1 : p->dealias == PST_DEALIAS_NONE ? m / 2 - 1 : (m + 2) / 3 - 1;
+    };
+    const int nx = ax_n(p, 0), ny = ax_n(p, 1), n = ax_n(p, 2);
+    P->geo = make_geo(nx, ny, n, cut(nx), cut(ny), cut(n), TWO_PI / ax_len(p, 0), TWO_PI / ax_len(p, 1),
+                      TWO_PI / ax_len(p, 2), gpe ? 1 : 0);
+    P->p.n = n;
+    const int K = P->geo.K, M = P->geo.M;
+    (void)M;
     const bool mhd = p->solver == PST_MHD, bq = p->solver == PST_BOUSSINESQ;
     // state components; fields of the backward passes (v, i k x v per vector
     // field; grad theta and theta; psi) and of the forward passes
@@ -533,7 +610,15 @@ extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst
     ALLOC(P->B, (size_t)P->nfin * P->geo.sb * es);
     ALLOC(P->C, (size_t)P->nfout * P->geo.sb * es);
     ALLOC(P->tw, (size_t)n * es);
-    const size_t nk2 = 3 * (size_t)K * K + 1;
+    P->twy = P->tw;
+    P->twx = P->tw;
+    if (P->geo.ny != n) ALLOC(P->twy, (size_t)P->geo.ny * es);
+    if (P->geo.nx != n) {
+        if (P->geo.nx == P->geo.ny) P->twx = P->twy;
+        else ALLOC(P->twx, (size_t)P->geo.nx * es);
+    }
+    const int Kmax = std::max(K, std::max(P->geo.Kx, P->geo.Ky));
+    const size_t nk2 = 3 * (size_t)Kmax * Kmax + 1;
     for (int i = 0; i < 2; ++i) {   // real factors; GPE: complex ones in the first pair
         ALLOC(P->Etab[i], nk2 * (gpe ? es : tsz));
         ALLOC(P->E2tab[i], nk2 * (gpe ? es : tsz));
@@ -557,10 +642,24 @@ extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst
     return PST_OK;
 }
 
+// shell width dk = the smallest a_i, and the shells a spectrum needs
+static double shell_dk(const Geo& g) { return std::min(g.ax, std::min(g.ay, g.az)); }
+static int shells_needed(const Geo& g) {
+    if (!g.aniso && g.Kx == g.K && g.Ky == g.K) return (int)floor(sqrt(3.0) * g.K + 0.5) + 1;
+    const double fx = g.ax * g.Kx, fy = g.ay * g.Ky, fz = g.az * g.K;
+    return (int)floor(sqrt(fx * fx + fy * fy + fz * fz) / shell_dk(g) + 0.5) + 1;
+}
+
 extern "C" pst_status pst_query(const pst_plan* P, pst_info* info) {
     if (!P || !info) return PST_ERR_INVALID_ARG;
     info->n = P->p.n;
     info->kcut = P->geo.K;
+    info->nx = P->geo.nx;
+    info->ny = P->geo.ny;
+    info->nz = P->geo.n;
+    info->kcut_x = P->geo.Kx;
+    info->kcut_y = P->geo.Ky;
+    info->nshells = shells_needed(P->geo);
     info->ncomp = P->ncomp;
     info->modes_per_comp = (size_t)P->geo.sc;
     info->workspace_bytes = P->owned_bytes;
@@ -601,7 +700,7 @@ static void launch_gather(pst_plan* P, const void* abi, void* st, int nc) {
 template <typename T>
 static void launch_scatter(pst_plan* P, const void* st, void* abi, int ncomp) {
     KTimer tm(P, PST_K_OTHER);
-    const int64_t tot = (int64_t)ncomp * P->p.n * P->p.n * (P->p.n / 2 + 1);
+    const int64_t tot = (int64_t)abi_spec_bytes(P, ncomp) / (int64_t)P->esz;
     hipLaunchKernelGGL((k_scatter<T>), dim3(grid_for(tot)), dim3(256), 0, P->stream, (const cx<T>*)st,
                        (cx<T>*)abi, P->geo, ncomp);
 }
@@ -621,11 +720,10 @@ extern "C" pst_status pst_set_state(pst_plan* P, int field, int space, const voi
     if (!valid_field(P, field)) return fail(P, PST_ERR_INVALID_ARG, "field %d invalid for this solver", field);
     if (space != PST_SPACE_PHYS && space != PST_SPACE_SPEC) return fail(P, PST_ERR_INVALID_ARG, "space %d", space);
     if (mem != PST_MEM_HOST && mem != PST_MEM_DEVICE) return fail(P, PST_ERR_INVALID_ARG, "mem %d", mem);
-    const size_t n = P->p.n;
     const int nc = field_nc(field);
     const size_t spec = abi_spec_bytes(P, nc);
     // physical data: real, or complex for the GPE wavefunction
-    const size_t phys = nc * n * n * n * (P->geo.full ? P->esz : P->esz / 2);
+    const size_t phys = nc * phys_points(P) * (P->geo.full ? P->esz : P->esz / 2);
     // layout of the scratch: [spectral (nc comps)] [physical staging if needed]
     const size_t need = spec + ((space == PST_SPACE_PHYS && mem == PST_MEM_HOST) ? phys : 0);
     pst_status s = ensure_abi(P, need);
@@ -643,8 +741,8 @@ extern "C" pst_status pst_set_state(pst_plan* P, int field, int space, const voi
             HIPCHK(P, hipMemcpyAsync(spec_buf + spec, src, phys, hipMemcpyHostToDevice, P->stream));
             phys_dev = spec_buf + spec;
         }
-        if (P->geo.full) P->L->fft_c2c(P, phys_dev, spec_buf, nc, 0);
-        else P->L->fft_r2c(P, phys_dev, spec_buf, nc);
+        if (P->geo.full) fft3_c2c(P, phys_dev, spec_buf, nc, 0);
+        else fft3_r2c(P, phys_dev, spec_buf, nc);
         if ((s = check_launch(P, "forward transform"))) return s;
     }
     char* st = (char*)P->U + (size_t)field_c0(field) * P->geo.sc * P->esz;
@@ -661,10 +759,9 @@ extern "C" pst_status pst_get_state(pst_plan* P, int field, int space, void* dst
     if (!valid_field(P, field)) return fail(P, PST_ERR_INVALID_ARG, "field %d invalid for this solver", field);
     if (space != PST_SPACE_PHYS && space != PST_SPACE_SPEC) return fail(P, PST_ERR_INVALID_ARG, "space %d", space);
     if (mem != PST_MEM_HOST && mem != PST_MEM_DEVICE) return fail(P, PST_ERR_INVALID_ARG, "mem %d", mem);
-    const size_t n = P->p.n;
     const int nc = field_nc(field);
     const size_t spec = abi_spec_bytes(P, nc);
-    const size_t phys = nc * n * n * n * (P->geo.full ? P->esz : P->esz / 2);
+    const size_t phys = nc * phys_points(P) * (P->geo.full ? P->esz : P->esz / 2);
     // scratch: [spectral] [c2r workspace (spectral)] [physical staging]
     const size_t need = space == PST_SPACE_SPEC ? spec : 2 * spec + (mem == PST_MEM_HOST ? phys : 0);
     pst_status s = ensure_abi(P, need);
@@ -682,8 +779,8 @@ extern "C" pst_status pst_get_state(pst_plan* P, int field, int space, void* dst
     } else {
         scatter(P, st, spec_buf, nc);
         void* target = mem == PST_MEM_DEVICE ? dst : (void*)(spec_buf + 2 * spec);
-        if (P->geo.full) P->L->fft_c2c(P, spec_buf, target, nc, 1);
-        else P->L->fft_c2r(P, spec_buf, target, nc, spec_buf + spec);
+        if (P->geo.full) fft3_c2c(P, spec_buf, target, nc, 1);
+        else fft3_c2r(P, spec_buf, target, nc, spec_buf + spec);
         if ((s = check_launch(P, "backward transform"))) return s;
         if (mem == PST_MEM_HOST) {
             HIPCHK(P, hipMemcpyAsync(dst, target, phys, hipMemcpyDeviceToHost, P->stream));
@@ -696,16 +793,19 @@ extern "C" pst_status pst_get_state(pst_plan* P, int field, int space, void* dst
 // forcing: keep the box |k_i| <= kf that holds every nonzero mode
 template <typename T>
 static pst_status set_forcing_t(pst_plan* P, const cx<T>* h /*host ABI layout*/) {
-    const int n = P->p.n, nxh = n / 2 + 1, K = P->geo.K;
+    const Geo& g = P->geo;
+    const int nx = g.nx, ny = g.ny, nz = g.n, nxh = nx / 2 + 1;
+    // element (c, z, y, x) of the ABI layout
+    auto at = [&](int c, int z, int y, int x) { return h[(((size_t)c * nz + z) * ny + y) * nxh + x]; };
     int kf = -1;
     for (int c = 0; c < 3; ++c)
-        for (int z = 0; z < n; ++z)
-            for (int y = 0; y < n; ++y)
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nxh; ++x) {
-                    const cx<T> v = h[(((size_t)c * n + z) * n + y) * nxh + x];
+                    const cx<T> v = at(c, z, y, x);
                     if (v.x == T(0) && v.y == T(0)) continue;
-                    const int ky = k_of_pos(y, n), kz = k_of_pos(z, n);
-                    if (x > K || abs(ky) > K || abs(kz) > K) continue;  // dealiased away
+                    const int ky = k_of_pos(y, ny), kz = k_of_pos(z, nz);
+                    if (x > g.Kx || abs(ky) > g.Ky || abs(kz) > g.K) continue;  // dealiased away
                     int m = x;
                     if (abs(ky) > m) m = abs(ky);
                     if (abs(kz) > m) m = abs(kz);
@@ -725,11 +825,14 @@ static pst_status set_forcing_t(pst_plan* P, const cx<T>* h /*host ABI layout*/)
         for (int kx = 0; kx <= kf; ++kx)
             for (int ky = -kf; ky <= kf; ++ky)
                 for (int kz = -kf; kz <= kf; ++kz) {
-                    const int y = (ky + n) % n, z = (kz + n) % n;
-                    cx<T> v = h[(((size_t)c * n + z) * n + y) * nxh + kx];
-                    if (kx == 0) {  // Hermitian part, as for the state
-                        const cx<T> m = h[(((size_t)c * n + (n - z) % n) * n + (n - y) % n) * nxh];
-                        v = {T(0.5) * (v.x + m.x), T(0.5) * (v.y - m.y)};
+                    cx<T> v = {T(0), T(0)};
+                    if (kx <= g.Kx && abs(ky) <= g.Ky && abs(kz) <= g.K) {   // kept on every axis
+                        const int y = (ky + ny) % ny, z = (kz + nz) % nz;
+                        v = at(c, z, y, kx);
+                        if (kx == 0) {  // Hermitian part, as for the state
+                            const cx<T> m = at(c, (nz - z) % nz, (ny - y) % ny, 0);
+                            v = {T(0.5) * (v.x + m.x), T(0.5) * (v.y - m.y)};
+                        }
                     }
                     box[c * fs + ((size_t)kx * w + (ky + kf)) * w + (kz + kf)] = v;
                 }
@@ -779,11 +882,11 @@ static pst_status run_rhs_passes(pst_plan* P, const void* state, int mode, void*
     pst_status s;
     P->L->zinv(P, state);
     if ((s = check_launch(P, "zinv"))) return s;
-    P->L->yinv(P);
+    P->Ly->yinv(P);
     if ((s = check_launch(P, "yinv"))) return s;
-    P->L->xpass(P);
+    P->Lx->xpass(P);
     if ((s = check_launch(P, "xpass"))) return s;
-    P->L->yfwd(P);
+    P->Ly->yfwd(P);
     if ((s = check_launch(P, "yfwd"))) return s;
     P->L->zfwd(P, mode, rhs_out);
     return check_launch(P, "zfwd");
@@ -876,19 +979,19 @@ extern "C" pst_status pst_spectrum(pst_plan* P, int field, double* Ek, int nshel
     if (!P) return PST_ERR_INVALID_ARG;
     if (!Ek) return fail(P, PST_ERR_INVALID_ARG, "Ek is NULL");
     if (!valid_field(P, field)) return fail(P, PST_ERR_INVALID_ARG, "field %d", field);
-    const int K = P->geo.K;
-    const int need = (int)floor(sqrt(3.0) * K + 0.5) + 1;
+    const int need = shells_needed(P->geo);
     if (nshells < need || nshells > MAX_SHELLS)
         return fail(P, PST_ERR_INVALID_ARG, "nshells must be in [%d, %d]", need, MAX_SHELLS);
     double* bins = P->red + RED_BLOCKS;
     {
         KTimer tm(P, PST_K_OTHER);
+        const double dk = shell_dk(P->geo);
         if (P->p.precision == PST_FP64)
             hipLaunchKernelGGL((k_spectrum<double>), dim3(nshells), dim3(RED_THREADS), 0, P->stream,
-                               (const cx<double>*)P->U, P->geo, field_c0(field), field_nc(field), bins);
+                               (const cx<double>*)P->U, P->geo, field_c0(field), field_nc(field), bins, dk);
         else
             hipLaunchKernelGGL((k_spectrum<float>), dim3(nshells), dim3(RED_THREADS), 0, P->stream,
-                               (const cx<float>*)P->U, P->geo, field_c0(field), field_nc(field), bins);
+                               (const cx<float>*)P->U, P->geo, field_c0(field), field_nc(field), bins, dk);
     }
     pst_status s = check_launch(P, "spectrum");
     if (s) return s;
@@ -904,7 +1007,7 @@ extern "C" pst_status pst_fft_r2c(pst_plan* P, const void* in, void* out, int nf
     if (!P) return PST_ERR_INVALID_ARG;
     if (!in || !out) return fail(P, PST_ERR_INVALID_ARG, "NULL buffer");
     if (nfields < 1) return fail(P, PST_ERR_INVALID_ARG, "nfields < 1");
-    P->L->fft_r2c(P, in, out, nfields);
+    fft3_r2c(P, in, out, nfields);
     return check_launch(P, "fft_r2c");
 }
 
@@ -914,7 +1017,7 @@ extern "C" pst_status pst_fft_c2r(pst_plan* P, const void* in, void* out, int nf
     if (nfields < 1) return fail(P, PST_ERR_INVALID_ARG, "nfields < 1");
     pst_status s = ensure_abi(P, abi_spec_bytes(P, nfields));
     if (s) return s;
-    P->L->fft_c2r(P, in, out, nfields, P->abi);
+    fft3_c2r(P, in, out, nfields, P->abi);
     return check_launch(P, "fft_c2r");
 }
 

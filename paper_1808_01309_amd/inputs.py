@@ -208,7 +208,8 @@ def plane_wave(shape, k=(1, 0, 0), amp=1.0, dtype=np.complex128):
     return out
 
 
-def random_scalar(n, seed, field=3, spectrum=spectrum_c2, energy=1.0, kcut=None, dtype=np.complex128):
+def random_scalar(n, seed, field=3, spectrum=spectrum_c2, energy=1.0, kcut=None, dtype=np.complex128,
+                  shape=None, box=None):
     """Random-phase real scalar field (temperature), spectral layout [n][n][n//2+1].
 
     For every stored mode k != 0 inside the cube |k_i| <= kcut:
@@ -216,20 +217,27 @@ def random_scalar(n, seed, field=3, spectrum=spectrum_c2, energy=1.0, kcut=None,
     t uniform in [0, 2 pi) from the counter-based generator (draw 0 of the
     given field id), the kx = 0 plane Hermitian as in random_solenoidal, and
     the amplitudes scaled to the variance 1/2 sum_k w |thetahat|^2 = energy.
+    shape = (nx, ny, nz), box = (Lx, Ly, Lz): anisotropic grid (layout
+    [nz][ny][nx//2+1], k the physical wavenumber, kcut None or per axis).
     """
+    nx, ny, nz = (n, n, n) if shape is None else shape
+    al = np.array([1.0, 1.0, 1.0]) if box is None else 2.0 * np.pi / np.asarray(box, float)
     if kcut is None:
-        kcut = kcut_23(n)
-    nxh = n // 2 + 1
-    out = np.zeros((n, n, nxh), dtype)
-    ks = np.arange(-kcut, kcut + 1)
-    kz2, ky2 = np.meshgrid(ks, ks, indexing="ij")
+        kc = (kcut_23(nx), kcut_23(ny), kcut_23(nz))
+    elif np.isscalar(kcut):
+        kc = (kcut,) * 3
+    else:
+        kc = tuple(kcut)
+    nxh = nx // 2 + 1
+    out = np.zeros((nz, ny, nxh), dtype)
+    kz2, ky2 = np.meshgrid(np.arange(-kc[2], kc[2] + 1), np.arange(-kc[1], kc[1] + 1), indexing="ij")
     kz2, ky2 = kz2.ravel(), ky2.ravel()
     planes = []
     e_tot = 0.0
-    for kx in range(min(kcut, n // 2) + 1):
+    for kx in range(min(kc[0], nx // 2) + 1):
         keep = ((ky2 > 0) | ((ky2 == 0) & (kz2 > 0))) if kx == 0 else np.ones(ky2.shape, bool)
         ky, kz = ky2[keep], kz2[keep]
-        k2 = (kx * kx + ky * ky + kz * kz).astype(np.float64)
+        k2 = ((al[0] * kx) ** 2 + (al[1] * ky) ** 2 + (al[2] * kz) ** 2).astype(np.float64)
         a2 = spectrum(np.sqrt(k2)) / (4.0 * np.pi * k2)
         e_tot += float(np.sum(a2))
         planes.append((kx, ky, kz, a2))
@@ -237,10 +245,10 @@ def random_scalar(n, seed, field=3, spectrum=spectrum_c2, energy=1.0, kcut=None,
     for kx, ky, kz, a2 in planes:
         t = 2.0 * np.pi * uniform(seed, field, np.full_like(ky, kx), ky, kz, 0)
         coef = np.sqrt(a2 * scale) * np.exp(1j * t)
-        iy, iz = np.mod(ky, n), np.mod(kz, n)
+        iy, iz = np.mod(ky, ny), np.mod(kz, nz)
         out[iz, iy, kx] = coef
         if kx == 0:
-            out[np.mod(-kz, n), np.mod(-ky, n), 0] = np.conj(coef)
+            out[np.mod(-kz, nz), np.mod(-ky, ny), 0] = np.conj(coef)
     return out
 
 
@@ -260,14 +268,22 @@ def gravity_wave_spec(n, k=(1, 1, 2), amp_u=0.1, amp_t=0.05, dtype=np.complex128
     return u, t
 
 
-def forcing_shells(n, seed, lo=2, hi=3, energy=1.0, kcut=None, dtype=np.complex128):
+def forcing_shells(n, seed, lo=2, hi=3, energy=1.0, kcut=None, dtype=np.complex128, shape=None, box=None):
     """Constant solenoidal random-phase forcing on shells lo..hi (seed + 1).
     Only the box |k_i| <= hi + 1 can hold those shells, so only it is drawn
-    (the draws are keyed by mode, so the result does not depend on the box)."""
-    if kcut is None:
-        kcut = kcut_23(n)
-    return random_solenoidal(n, seed + 1, field=7, spectrum=flat_shells(lo, hi),
-                             energy=energy, kcut=min(kcut, hi + 1), dtype=dtype)
+    (the draws are keyed by mode, so the result does not depend on the box).
+    shape / box: anisotropic grid; the drawn box is then |a_i k_i| <= hi + 1
+    on each axis (a_i = 2 pi / L_i), within the axis cutoffs."""
+    if shape is None:
+        if kcut is None:
+            kcut = kcut_23(n)
+        return random_solenoidal(n, seed + 1, field=7, spectrum=flat_shells(lo, hi),
+                                 energy=energy, kcut=min(kcut, hi + 1), dtype=dtype)
+    al = [1.0, 1.0, 1.0] if box is None else [2.0 * np.pi / L for L in box]
+    kc = [kcut_23(m) for m in shape] if kcut is None else list(kcut)
+    kc = tuple(min(kc[i], int(np.ceil((hi + 1) / al[i]))) for i in range(3))
+    return random_solenoidal(0, seed + 1, field=7, spectrum=flat_shells(lo, hi), energy=energy, kcut=kc,
+                             dtype=dtype, shape=shape, box=box)
 
 
 # ------------------------------------------------------------ analytic fields

@@ -43,14 +43,18 @@ class pst_params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("solver", ctypes.c_int), ("precision", ctypes.c_int),
                 ("rk_order", ctypes.c_int), ("nu", ctypes.c_double), ("eta", ctypes.c_double),
                 ("dt", ctypes.c_double), ("dealias", ctypes.c_int), ("flags", ctypes.c_uint),
-                ("nbv", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double)]
+                ("nbv", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double)]
 
 
 class pst_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("kcut", ctypes.c_int), ("ncomp", ctypes.c_int),
                 ("modes_per_comp", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
                 ("radices", ctypes.c_int * 4), ("tile_lines", ctypes.c_int),
-                ("steps_done", ctypes.c_longlong)]
+                ("steps_done", ctypes.c_longlong), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("nz", ctypes.c_int), ("kcut_x", ctypes.c_int), ("kcut_y", ctypes.c_int),
+                ("nshells", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -185,19 +189,24 @@ class Plan:
 
     def __init__(self, n, solver="ns", precision="fp32", rk_order=4, nu=0.0, eta=None, dt=1e-3,
                  linear_only=False, timers=False, stream=None, dealias="cube", kappa=None, nbv=0.0,
-                 alpha=0.0, beta=0.0):
+                 alpha=0.0, beta=0.0, shape=None, box=None):
         """solver: "ns", "mhd" (eta: magnetic diffusivity), "boussinesq"
         (kappa: scalar diffusivity, default nu; nbv: Brunt-Vaisala frequency)
-        or "gpe" (d psi/dt = i alpha Lap psi - i beta |psi|^2 psi)."""
+        or "gpe" (d psi/dt = i alpha Lap psi - i beta |psi|^2 psi).
+        shape = (nx, ny, nz) and box = (Lx, Ly, Lz) give an anisotropic grid
+        (n is then ignored where shape is given); default n^3 on [0, 2 pi)^3."""
+        nx, ny, nz = (n, n, n) if shape is None else shape
+        lx, ly, lz = (0.0, 0.0, 0.0) if box is None else box
         second = kappa if solver == "boussinesq" else eta
         p = pst_params(n=n, solver=_SOLVERS[solver],
                        precision=PST_FP64 if precision == "fp64" else PST_FP32, rk_order=rk_order,
                        nu=nu, eta=nu if second is None else second, dt=dt,
                        dealias={"cube": 0, "sphere": 1, "none": 2}[dealias],
                        flags=(PST_FLAG_LINEAR_ONLY if linear_only else 0) | (PST_FLAG_TIMERS if timers else 0),
-                       nbv=nbv, alpha=alpha, beta=beta)
+                       nbv=nbv, alpha=alpha, beta=beta, nx=nx, ny=ny, nz=nz, lx=lx, ly=ly, lz=lz)
         self.params = p
-        self.n = n
+        self.n = nz
+        self.shape = (nx, ny, nz)
         self.fp64 = precision == "fp64"
         self.mhd = solver == "mhd"
         self.solver = solver
@@ -233,10 +242,12 @@ class Plan:
 
     def spec_shape(self, ncomp=3):
         # GPE: the whole spectrum of a complex field
-        return (ncomp, self.n, self.n, self.n if self.gpe else self.n // 2 + 1)
+        nx, ny, nz = self.shape
+        return (ncomp, nz, ny, nx if self.gpe else nx // 2 + 1)
 
     def phys_shape(self, ncomp=3):
-        return (ncomp, self.n, self.n, self.n)
+        nx, ny, nz = self.shape
+        return (ncomp, nz, ny, nx)
 
     def _phys_np(self):
         return self.cplx_np if self.gpe else self.real_np
@@ -316,7 +327,7 @@ class Plan:
         if field is None:
             field = "psi" if self.gpe else "u"
         if nshells is None:
-            nshells = int(np.floor(np.sqrt(3.0) * self.query()["kcut"] + 0.5)) + 1
+            nshells = self.query()["nshells"]
         out = np.zeros(nshells, np.float64)
         self._check(lib.pst_spectrum(self._h, _FIELDS[field], out.ctypes.data_as(_P), nshells))
         return out
@@ -341,7 +352,8 @@ class Plan:
         return {"n": info.n, "kcut": info.kcut, "ncomp": info.ncomp,
                 "modes_per_comp": info.modes_per_comp, "workspace_bytes": info.workspace_bytes,
                 "radices": [r for r in info.radices if r], "tile_lines": info.tile_lines,
-                "steps_done": info.steps_done}
+                "steps_done": info.steps_done, "shape": (info.nx, info.ny, info.nz),
+                "kcuts": (info.kcut_x, info.kcut_y, info.kcut), "nshells": info.nshells}
 
     def timers(self, reset=True):
         ms = np.zeros(len(KERNEL_KINDS), np.float64)

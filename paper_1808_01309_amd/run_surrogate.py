@@ -93,6 +93,10 @@ def run(argv=None):
         "solver_windows": h["solver_windows"], "audit_fail": h["audit_fail"], "guard_fail": h["guard_fail"],
         "max_one_application_err": max(res["windows"]["one_step_err"]),
         "final_rel_l2_vs_plain_max": max(h["final_rel_l2"]) if "final_rel_l2" in h else None,
+        # the horizon reading: speed-up while the hybrid stays within 1e-2 of the plain rollout
+        "matched_windows": h.get("matched_windows"), "matched_steps": h.get("matched_steps"),
+        "matched_speedup": h.get("matched_speedup"), "matched_max_err": h.get("matched_max_err"),
+        "matched_surrogate_windows": h.get("matched_surrogate_windows"),
     }
     fno.close()
     return res

@@ -134,6 +134,9 @@ def rollout(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4, tol=1e-
     y = torch.empty_like(x)
     stats = {"apps": apps, "horizon": horizon, "guard_fail": 0, "audits": 0, "audit_fail": 0,
              "solver_windows": 0, "audit_err": []}
+    # per window: wall time since the start, who advanced it, and the state
+    # (kept on the device for the untimed comparison with the plain rollout)
+    t_win, by_sur, states = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solver_next = False
@@ -150,6 +153,10 @@ def rollout(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4, tol=1e-
             sol_has_x = True
             stats["solver_windows"] += 1
             solver_next = False
+            t_win.append(time.perf_counter() - t0)
+            by_sur.append(False)
+            if reference:
+                states.append(x.clone())
             continue
         fno.forward(x, y)
         sur.load(y, project=True)
@@ -174,10 +181,18 @@ def rollout(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4, tol=1e-
                 e_in, z_in = sol.ens.diagnostics()
                 sol_has_x = True
                 solver_next = True
+                t_win.append(time.perf_counter() - t0)
+                by_sur.append(False)
+                if reference:
+                    states.append(x.clone())
                 continue
         sur.store(x)
         e_in, z_in = e1, z1
         sol_has_x = False
+        t_win.append(time.perf_counter() - t0)
+        by_sur.append(True)
+        if reference:
+            states.append(x.clone())
     torch.cuda.synchronize()
     stats["t_hybrid_s"] = time.perf_counter() - t0
     if reference:
@@ -196,7 +211,38 @@ def rollout(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4, tol=1e-
         chk.load(x)
         stats["final_rel_l2"] = chk.ens.rel_l2(ref.ens).tolist()
         stats["speedup"] = stats["t_plain_s"] / stats["t_hybrid_s"]
+        # untimed: the hybrid's error against the plain rollout after every window
+        ref.load(init_phys)
+        win_err = []
+        for w in range(apps):
+            ref.ens.step(horizon)
+            chk.load(states[w])
+            win_err.append(float(chk.ens.rel_l2(ref.ens).max()))
+        stats["window_err_vs_plain"] = win_err
+        stats["window_time_s"] = t_win
+        stats["window_by_surrogate"] = by_sur
+        stats.update(matched_horizon(stats, tol))
     return stats
+
+
+def matched_horizon(stats, tol):
+    """Speed-up over the horizon in which the hybrid stays within `tol` of the
+    plain rollout: the first w windows whose errors (against the plain solver
+    at the same time) are all <= tol; plain time of those w windows (its mean
+    time per step) over the hybrid's wall time for them."""
+    err = stats["window_err_vs_plain"]
+    w = 0
+    while w < len(err) and err[w] <= tol:
+        w += 1
+    out = {"tol": tol, "matched_windows": w, "matched_steps": w * stats["horizon"]}
+    if w > 0:
+        t_plain = stats["t_plain_s"] * w / stats["apps"]
+        out["matched_speedup"] = t_plain / stats["window_time_s"][w - 1]
+        out["matched_max_err"] = max(err[:w])
+        out["matched_surrogate_windows"] = int(sum(stats["window_by_surrogate"][:w]))
+    else:
+        out["matched_speedup"] = None
+    return out
 
 
 def window_errors(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4):

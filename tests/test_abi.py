@@ -61,6 +61,9 @@ def _create(pst, **kw):
     (dict(dt=0.0), 1), (dict(dt=-1.0), 1), (dict(nu=-1.0), 1), (dict(nu=float("nan")), 1),
     (dict(solver=1, eta=-2.0), 1), (dict(solver=2, eta=-1.0), 1), (dict(solver=2, nbv=float("inf")), 1),
     (dict(dealias=3), 6), (dict(flags=0x100), 1),
+    (dict(nx=40), 2), (dict(nz=7), 2), (dict(ny=-2), 1), (dict(lx=-1.0), 1), (dict(lz=float("nan")), 1),
+    (dict(ny=16, dealias=1), 6), (dict(ly=3.0, dealias=1), 6), (dict(solver=3, dealias=1), 6),
+    (dict(solver=3, alpha=float("inf")), 1),
 ])
 def test_plan_create_rejects_bad_params(pst, kw, status):
     s, h = _create(pst, **kw)
