@@ -42,8 +42,9 @@ template <typename T> constexpr int tile_lines() { return sizeof(T) == 4 ? 16 : 
 // each halve the tile so the block stays within the register file.
 template <typename T, bool MHD, int N>
 constexpr int xpass_lines() {
-    // FP32 Navier-Stokes below n = 1024: 8 lines, two workgroups per CU
-    if (sizeof(T) == 4 && !MHD && N < 1024) return 8;
+    // FP32 Navier-Stokes: 8 lines below n = 1024, 4 at 1024 (128 threads per
+    // line there), two workgroups per CU
+    if (sizeof(T) == 4 && !MHD) return N < 1024 ? 8 : 4;
     return tile_lines<T>() / (MHD ? 2 : 1) / (N >= 1024 ? 2 : 1);
 }
 constexpr int LINE_BLOCK = 256;
@@ -77,6 +78,12 @@ template <typename T, int N, bool MHD> struct XPlan {
     static constexpr int G = NCfg<N>::G;
 };
 template <> struct XPlan<float, 1024, true> {
+    using P = Radices<8, 8, 4, 4>;
+    static constexpr int G = 128;
+};
+// Navier-Stokes at n = 1024 likewise: 8 points per thread keep the three
+// pairs of a line in about the registers of the 512-point pass
+template <> struct XPlan<float, 1024, false> {
     using P = Radices<8, 8, 4, 4>;
     static constexpr int G = 128;
 };
@@ -385,23 +392,46 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
             const int p = FI::first_pos(g, e);
             const bool lo = p <= K, hi = p >= N - K;
             // SPLIT: p = g + d with d = first_pos(0, e) a multiple of 8, so
-            // kk = g + d or N - g - d splits as at() needs.  Branch-free: every
-            // lane reads a valid row (row 0 for the points between the kept
-            // bands) and the result is selected.
+            // kk = g + d or N - g - d splits as at() needs.  FP32 Navier-Stokes:
+            // branch-free, every lane reads a valid row (row 0 for the points
+            // between the kept bands) and the result is selected (fewer scalar
+            // branch instructions: 1.30 -> 1.27 ms at 512^3); the others branch
+            // (selecting both alternatives costs them registers: FP64 spilled,
+            // MHD and Boussinesq measured 3-5% slower).
             const bool in = lo || hi;
-            const int d = FI::first_pos(0, e), kk = !in ? 0 : lo ? p : N - p;
-            cx<T> U, W;
-            if constexpr (SPLIT) {
-                const int b0 = !in ? 0 : lo ? g : N - g, dd = !in ? 0 : lo ? d : -d;
-                U = stage.at(b0, dd);
-                W = stage.at(K + 1 + b0, dd);
+            const int d = FI::first_pos(0, e);
+            if constexpr (sizeof(T) == 4 && SYS == 0) {
+                const int kk = !in ? 0 : lo ? p : N - p;
+                cx<T> U, W;
+                if constexpr (SPLIT) {
+                    const int b0 = !in ? 0 : lo ? g : N - g, dd = !in ? 0 : lo ? d : -d;
+                    U = stage.at(b0, dd);
+                    W = stage.at(K + 1 + b0, dd);
+                } else {
+                    U = stage(kk);
+                    W = stage(K + 1 + kk);
+                }
+                cx<T> Z = lo ? cx<T>{U.x - W.y, U.y + W.x} : cx<T>{U.x + W.y, W.x - U.y};
+                if (p == 0) Z = {U.x, W.x};
+                v[pi][e] = in ? Z : czero<T>();
             } else {
-                U = stage(kk);
-                W = stage(K + 1 + kk);
+                const int kk = lo ? p : N - p;
+                cx<T> Z = czero<T>();
+                if (in) {
+                    cx<T> U, W;
+                    if constexpr (SPLIT) {
+                        U = lo ? stage.at(g, d) : stage.at(N - g, -d);
+                        W = lo ? stage.at(K + 1 + g, d) : stage.at(K + 1 + N - g, -d);
+                    } else {
+                        U = stage(kk);
+                        W = stage(K + 1 + kk);
+                    }
+                    if (p == 0) Z = {U.x, W.x};
+                    else if (lo) Z = {U.x - W.y, U.y + W.x};
+                    else Z = {U.x + W.y, W.x - U.y};
+                }
+                v[pi][e] = Z;
             }
-            cx<T> Z = lo ? cx<T>{U.x - W.y, U.y + W.x} : cx<T>{U.x + W.y, W.x - U.y};
-            if (p == 0) Z = {U.x, W.x};
-            v[pi][e] = in ? Z : czero<T>();
         }
         if constexpr (!PPB) __syncthreads();
         ++ex;
@@ -459,11 +489,10 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
         __syncthreads();
         if (zin) {
             const int fa = 2 * po, fb = 2 * po + 1;
-            // rows kx = g + i G <= K (a fixed, predicated count)
-#pragma unroll
-            for (int i = 0; i < IT; ++i) {
+            // rows kx = g + i G <= K: FP32 a fixed, predicated count (unrolled),
+            // FP64 a loop (fewer live registers)
+            auto out_row = [&](int i) {
                 const int kx = g + i * G, d = i * G;
-                if (kx > K) continue;
                 cx<T> a, b;
                 if constexpr (SPLIT) {
                     a = lo.at(g, d);
@@ -478,6 +507,13 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
                     const cx<T> Bv = {T(0.5) * (a.y + b.y), T(-0.5) * (a.x - b.x)};
                     Cf[fb * geo.sb + kx * nn + off] = Bv;
                 }
+            };
+            if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                for (int i = 0; i < IT; ++i)
+                    if (g + i * G <= K) out_row(i);
+            } else {
+                for (int i = 0; g + i * G <= K; ++i) out_row(i);
             }
         }
         if constexpr (!PPB) __syncthreads();
@@ -496,20 +532,20 @@ template <typename T, class CF, bool MHD> constexpr bool xpass_pp() {
     return !MHD && 2 * xtile_lds<T, CF, CF::G * CF::TL>() * (int)sizeof(cx<T>) <= 160 * 1024;
 }
 
-// Two workgroups per CU for the FP32 Navier-Stokes x pass below n = 1024: its
-// 8-line tile fits 128 VGPRs, so two tiles are in flight per CU and one's
-// loads overlap the other's transforms (1.52 -> 1.49 ms at 512^3 against one
-// 16-line tile per CU).
+// Two workgroups per CU for the FP32 Navier-Stokes x pass: its tile (8 lines
+// of 64 threads below n = 1024, 4 lines of 128 threads at 1024) fits 128
+// VGPRs, so two tiles are in flight per CU and one's loads overlap the
+// other's transforms (1.52 -> 1.49 ms at 512^3 against one 16-line tile per CU).
 template <typename T, int N, int SYS> constexpr bool xpass_two_per_cu() {
-    return SYS == 0 && sizeof(T) == 4 && N < 1024;
+    return SYS == 0 && sizeof(T) == 4;
 }
 
 // Tiles per workgroup: FP64 and the other half-height FP32 tiles (Boussinesq,
 // n = 1024) loop over 32 consecutive tiles, which overlaps one tile's final
 // stores with the next tile's first reads (measured 11% faster for FP64
 // Navier-Stokes and the FP32 Boussinesq x pass at 512^3); MHD and the FP32
-// Navier-Stokes tiles below 1024 take one tile (a loop costs them registers
-// and occupancy).
+// Navier-Stokes tiles take one tile (a loop costs them registers and
+// occupancy).
 template <typename T, class CF, int SYS> constexpr int xpass_per() {
     if constexpr (xpass_two_per_cu<T, CF::N, SYS>()) return 1;
     else return ((sizeof(T) == 8 || CF::TL < tile_lines<T>()) && xpass_pp<T, CF, SYS == 1>()) ? 32 : 1;
@@ -580,7 +616,10 @@ __device__ __forceinline__ void rk_apply(int mode, cx<T>* __restrict__ U, cx<T>*
     }
 }
 
-template <typename T, class CF, int NT, int SYS>
+// ANI: a non-cubic grid or box (|k|^2 not an integer): the integrating
+// factors are evaluated per mode; a separate instantiation keeps the FP64 path
+// out of the cubic kernels' register allocation.
+template <typename T, class CF, int NT, int SYS, bool ANI = false>
 __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw, const Geo& geo,
                                            const RkArgs<T>& ra, cx<T>* __restrict__ U, cx<T>* __restrict__ V,
                                            cx<T>* __restrict__ Acc, cx<T>* __restrict__ R, int mode, int64_t unit,
@@ -611,7 +650,7 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
     const T scale = T(1) / (T(geo.nx) * T(geo.ny) * T(N));
     // physical wavenumbers a_i k_i (equal to the integers on the 2 pi box)
     const T fkx = T(geo.ax) * T(kx), fky = T(geo.ay) * T(iky);
-    const double kxy2 = geo.ax * geo.ax * kx * kx + geo.ay * geo.ay * iky * iky;
+    const double kxy2 = ANI ? geo.ax * geo.ax * kx * kx + geo.ay * geo.ay * iky * iky : 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int q = F::last_pos(g, e);
@@ -648,7 +687,7 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
         // rounded once; loaded once per mode for all components (the
         // stage-array stores in between would otherwise force reloads)
         T Eu, E2u;
-        if (!geo.aniso) {
+        if constexpr (!ANI) {
             Eu = ra.E[0][k2];
             E2u = ra.E2[0][k2];
         } else {
@@ -658,7 +697,7 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
         }
         // the second group's factors (b, theta), loaded where they are used
         auto second_if = [&](T& Eb, T& E2b) {
-            if (!geo.aniso) {
+            if constexpr (!ANI) {
                 Eb = ra.E[1][k2];
                 E2b = ra.E2[1][k2];
             } else {
@@ -694,17 +733,17 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
 }
 
 // SYS: 0 Navier-Stokes, 1 MHD, 2 Boussinesq.
-template <typename T, class CF, int NT, int SYS>
+template <typename T, class CF, int NT, int SYS, bool ANI = false>
 __device__ __forceinline__ void zfwd_body(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw, const Geo& geo,
                                           const RkArgs<T>& ra, int mode, int64_t unit, int tid, cx<T>* sm) {
-    zfwd_lines<T, CF, NT, SYS>(D, tw, geo, ra, ra.U, ra.V, ra.Acc, ra.R, mode, unit, tid, sm);
+    zfwd_lines<T, CF, NT, SYS, ANI>(D, tw, geo, ra, ra.U, ra.V, ra.Acc, ra.R, mode, unit, tid, sm);
 }
 
-template <typename T, class CF, int SYS>
+template <typename T, class CF, int SYS, bool ANI>
 __global__ __launch_bounds__(LINE_BLOCK) void k_zfwd(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw,
                                                       Geo geo, RkArgs<T> ra, int mode) {
     __shared__ cx<T> sm[line_lds<T, CF, LINE_BLOCK>()];
-    zfwd_body<T, CF, LINE_BLOCK, SYS>(D, tw, geo, ra, mode, blockIdx.x, threadIdx.x, sm);
+    zfwd_body<T, CF, LINE_BLOCK, SYS, ANI>(D, tw, geo, ra, mode, blockIdx.x, threadIdx.x, sm);
 }
 
 // ------------------------------------------------------------ standalone FFTs
@@ -1003,7 +1042,9 @@ __device__ __forceinline__ void xpass_gpe_body(const cx<T>* __restrict__ Bf, cx<
     const int y = valid ? (int)(tile / NTZ) : 0;
     const int z = zt * TL + t;
     const bool zin = valid && z < nz;
-    const TileBlk<T, TL> lds{sm + s * TileBlk<T, TL>::size(N) + t};
+    // two LDS buffers used by alternate exchanges: one barrier per exchange
+    constexpr int TSZ1 = TileBlk<T, TL>::size(N), TSZ = SG * TSZ1;
+    const TileBlk<T, TL> lds0{sm + s * TSZ1 + t}, lds1{sm + TSZ + s * TSZ1 + t};
     const int64_t nn = (int64_t)geo.ny * nz, off = (int64_t)y * nz + z;
     cx<T> v[E];
 #pragma unroll
@@ -1011,13 +1052,13 @@ __device__ __forceinline__ void xpass_gpe_body(const cx<T>* __restrict__ Bf, cx<
         const int j = jx_of_pos(FI::first_pos(g, e), geo);
         v[e] = (zin && j >= 0) ? Bf[j * nn + off] : czero<T>();
     }
-    FI::run(v, g, lds, tw);
+    FI::run_pp(v, g, lds0, lds1, 0, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const T a2 = v[e].x * v[e].x + v[e].y * v[e].y;
         v[e] = {a2 * v[e].x, a2 * v[e].y};
     }
-    FF::run(v, g, lds, tw);
+    FF::run_pp(v, g, lds0, lds1, FI::EXCH, tw);
     if (zin) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -1027,10 +1068,15 @@ __device__ __forceinline__ void xpass_gpe_body(const cx<T>* __restrict__ Bf, cx<
     }
 }
 
+// Half-height tiles (8 lines FP32, 4 FP64) so that the two exchange buffers
+// of a block fit twice per CU.
+template <typename T, int N>
+using GpeXCfg = KCfg<typename NCfg<N>::P, NCfg<N>::G, tile_lines<T>() / 2>;
+
 template <typename T, class CF>
 __global__ __launch_bounds__((CF::G * CF::TL)) void k_xpass_gpe(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
                                                                const cx<T>* __restrict__ tw, Geo geo) {
-    __shared__ cx<T> sm[xtile_lds<T, CF, CF::G * CF::TL>()];
+    __shared__ cx<T> sm[2 * xtile_lds<T, CF, CF::G * CF::TL>()];
     xpass_gpe_body<T, CF, CF::G * CF::TL>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm);
 }
 
@@ -1077,7 +1123,7 @@ __device__ __forceinline__ void rk_apply_cx(int mode, cx<T>* __restrict__ U, cx<
     }
 }
 
-template <typename T, class CF, int NT>
+template <typename T, class CF, int NT, bool ANI>
 __device__ __forceinline__ void zfwd_gpe_lines(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw,
                                                const Geo& geo, const RkArgs<T>& ra, cx<T>* __restrict__ U,
                                                cx<T>* __restrict__ V, cx<T>* __restrict__ Acc, cx<T>* __restrict__ R,
@@ -1100,7 +1146,7 @@ __device__ __forceinline__ void zfwd_gpe_lines(const cx<T>* __restrict__ D, cons
     if (!active) return;
     // -i beta F[|psi|^2 psi] with the forward scale 1/(nx ny nz)
     const T sb = ra.beta / (T(geo.nx) * T(geo.ny) * T(N));
-    const double kxy2 = geo.ax * geo.ax * ikx * ikx + geo.ay * geo.ay * iky * iky;
+    const double kxy2 = ANI ? geo.ax * geo.ax * ikx * ikx + geo.ay * geo.ay * iky * iky : 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int q = F::last_pos(g, e);
@@ -1111,7 +1157,7 @@ __device__ __forceinline__ void zfwd_gpe_lines(const cx<T>* __restrict__ D, cons
         cx<T> nk = {sb * v[e].y, -sb * v[e].x};
         if (ra.lin_only) nk = czero<T>();
         cx<T> Ef, E2f;
-        if (!geo.aniso) {
+        if constexpr (!ANI) {
             Ef = ra.Ec[k2];
             E2f = ra.E2c[k2];
         } else {   // exp(-i alpha |k|^2 h / 2) in FP64, rounded once
@@ -1126,11 +1172,12 @@ __device__ __forceinline__ void zfwd_gpe_lines(const cx<T>* __restrict__ D, cons
     }
 }
 
-template <typename T, class CF>
+template <typename T, class CF, bool ANI>
 __global__ __launch_bounds__(LINE_BLOCK) void k_zfwd_gpe(const cx<T>* __restrict__ D, const cx<T>* __restrict__ tw,
                                                           Geo geo, RkArgs<T> ra, int mode) {
     __shared__ cx<T> sm[line_lds<T, CF, LINE_BLOCK>()];
-    zfwd_gpe_lines<T, CF, LINE_BLOCK>(D, tw, geo, ra, ra.U, ra.V, ra.Acc, ra.R, mode, blockIdx.x, threadIdx.x, sm);
+    zfwd_gpe_lines<T, CF, LINE_BLOCK, ANI>(D, tw, geo, ra, ra.U, ra.V, ra.Acc, ra.R, mode, blockIdx.x, threadIdx.x,
+                                           sm);
 }
 
 // Contiguous complex lines of N points, one line per G threads: the x pass of
@@ -1204,7 +1251,9 @@ struct Impl {
         KTimer tm(P, PST_K_XPASS);
         const Geo& g = P->geo;
         if (P->p.solver == PST_GPE) {
-            hipLaunchKernelGGL((k_xpass_gpe<T, TC>), dim3((unsigned)xtile_units<TC, TB>(g)), dim3(TB), 0, P->stream,
+            using GC = GpeXCfg<T, N>;
+            constexpr int GB = GC::G * GC::TL;
+            hipLaunchKernelGGL((k_xpass_gpe<T, GC>), dim3((unsigned)xtile_units<GC, GB>(g)), dim3(GB), 0, P->stream,
                                (const cx<T>*)P->B, (cx<T>*)P->C, (const cx<T>*)twid(P), g);
         } else if (P->p.solver == PST_MHD) {
             using XC = XCfg<T, N, true>;
@@ -1260,18 +1309,24 @@ struct Impl {
         ra.visc[0] = P->p.solver == PST_GPE ? P->p.alpha : P->p.nu;
         ra.visc[1] = P->p.eta;
         ra.hd = P->p.dt;
+        if (g.aniso) zfwd_launch<true>(P, ra, mode);
+        else zfwd_launch<false>(P, ra, mode);
+    }
+    template <bool ANI>
+    static void zfwd_launch(pst_plan* P, const RkArgs<T>& ra, int mode) {
+        const Geo& g = P->geo;
         const unsigned nb = (unsigned)line_units<LC, LINE_BLOCK>(g);
         if (P->p.solver == PST_GPE)
-            hipLaunchKernelGGL((k_zfwd_gpe<T, LC>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
-                               (const cx<T>*)twid(P), g, ra, mode);
+            hipLaunchKernelGGL((k_zfwd_gpe<T, LC, ANI>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream,
+                               (const cx<T>*)P->A, (const cx<T>*)twid(P), g, ra, mode);
         else if (P->p.solver == PST_MHD)
-            hipLaunchKernelGGL((k_zfwd<T, LC, 1>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+            hipLaunchKernelGGL((k_zfwd<T, LC, 1, ANI>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
                                (const cx<T>*)twid(P), g, ra, mode);
         else if (P->p.solver == PST_BOUSSINESQ)
-            hipLaunchKernelGGL((k_zfwd<T, LC, 2>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+            hipLaunchKernelGGL((k_zfwd<T, LC, 2, ANI>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
                                (const cx<T>*)twid(P), g, ra, mode);
         else
-            hipLaunchKernelGGL((k_zfwd<T, LC, 0>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
+            hipLaunchKernelGGL((k_zfwd<T, LC, 0, ANI>), dim3(nb), dim3(LINE_BLOCK), 0, P->stream, (const cx<T>*)P->A,
                                (const cx<T>*)twid(P), g, ra, mode);
     }
     // One axis of the standalone 3D transforms (the runtime composes x, y, z
