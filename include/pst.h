@@ -213,6 +213,15 @@ pst_status pst_energy(pst_plan *plan, double out[2]);
  * Synchronous.  NONFINITE if either is NaN/Inf. */
 pst_status pst_enstrophy(pst_plan *plan, double out[2]);
 
+/* Dealias and project ngroups vector fields given in the spectral layout
+ * ([ngroups][3][nz][ny][nx/2+1], device, the plan's precision), in place: modes
+ * outside the dealiasing cube are zeroed, the others projected onto
+ * divergence-free fields (Sec. 2: pressure by projection; the k = 0 mode is
+ * kept).  energy / enstrophy (host double[ngroups], either may be NULL) receive
+ * 1/2 sum w |v|^2 and 1/2 sum w |k|^2 |v|^2 of each projected group; the call
+ * is then synchronous, else stream-ordered.  UNSUPPORTED for GPE plans. */
+pst_status pst_project(pst_plan *plan, void *spec_dev, int ngroups, double *energy, double *enstrophy);
+
 /* Shell spectrum E(s) = 1/2 sum_{floor(|k|+1/2) = s} w |vhat|^2 for
  * s = 0..nshells-1 (double; GPE: the number spectrum sum_shell |psihat|^2),
  * summed in a fixed order (bitwise repeatable).

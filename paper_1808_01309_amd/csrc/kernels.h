@@ -651,6 +651,11 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
     // physical wavenumbers a_i k_i (equal to the integers on the 2 pi box)
     const T fkx = T(geo.ax) * T(kx), fky = T(geo.ay) * T(iky);
     const double kxy2 = ANI ? geo.ax * geo.ax * kx * kx + geo.ay * geo.ay * iky * iky : 0.0;
+    // kx^2 + ky^2: uniform over a wavefront when a line fills whole
+    // wavefronts (G >= 64), so its table entries come through scalar loads
+    // into scalar registers
+    int kp2 = kx * kx + iky * iky;
+    if constexpr (G >= 64) kp2 = __builtin_amdgcn_readfirstlane(kp2);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int q = F::last_pos(g, e);
@@ -682,14 +687,19 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
             for (int c = 0; c < 3; ++c) o[c] = cadd(o[c], ra.F[c * fs + fi]);
         }
         if (ra.lin_only) o[0] = o[1] = o[2] = czero<T>();
-        // integrating factors: by integer |k|^2 from the tables (2 pi box) or,
-        // on other boxes, exp(-visc |k|^2 h / 2) evaluated here in FP64 and
-        // rounded once; loaded once per mode for all components (the
-        // stage-array stores in between would otherwise force reloads)
+        // integrating factors: on the 2 pi box the product of the tables at
+        // kx^2 + ky^2 (one entry per line) and at kz^2 (the same few entries
+        // for every line), exp(-c |k|^2) = exp(-c k_perp^2) exp(-c kz^2): a
+        // direct lookup by |k|^2 scatters over the whole table, which at
+        // n = 1024 (1.4 MB per table) L2 does not keep and fetched again
+        // (1.55x the algorithmic bytes of the MHD pass); on other boxes
+        // exp(-visc |k|^2 h / 2) evaluated here in FP64 and rounded once.
+        // Loaded once per mode for all components (the stage-array stores in
+        // between would otherwise force reloads).
         T Eu, E2u;
         if constexpr (!ANI) {
-            Eu = ra.E[0][k2];
-            E2u = ra.E2[0][k2];
+            Eu = ra.E[0][kp2] * ra.E[0][ikz * ikz];
+            E2u = ra.E2[0][kp2] * ra.E2[0][ikz * ikz];
         } else {
             const double eu = exp(-0.5 * ra.visc[0] * ra.hd * (kxy2 + geo.az * geo.az * ikz * ikz));
             Eu = T(eu);
@@ -698,8 +708,8 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
         // the second group's factors (b, theta), loaded where they are used
         auto second_if = [&](T& Eb, T& E2b) {
             if constexpr (!ANI) {
-                Eb = ra.E[1][k2];
-                E2b = ra.E2[1][k2];
+                Eb = ra.E[1][kp2] * ra.E[1][ikz * ikz];
+                E2b = ra.E2[1][kp2] * ra.E2[1][ikz * ikz];
             } else {
                 const double eb = exp(-0.5 * ra.visc[1] * ra.hd * (kxy2 + geo.az * geo.az * ikz * ikz));
                 Eb = T(eb);

@@ -971,6 +971,128 @@ static pst_status quadratic_diag(pst_plan* P, double out[2], int k2w, const char
     return PST_OK;
 }
 
+// ------------------------------------------------------------ projection of spectral fields
+// In place on the ABI spectral layout [ngroups][3][nz][ny][nx/2+1]: every mode
+// outside the dealiasing cube is zeroed, the others are projected onto
+// divergence-free fields, v - k (k . v) / |k|^2 (k = 0 kept).
+template <typename T>
+__global__ void k_project_abi(cx<T>* __restrict__ spec, Geo g, int ngroups) {
+    const int nx = g.nx, ny = g.ny, nz = g.n, nxh = nx / 2 + 1;
+    const int64_t per = (int64_t)nz * ny * nxh, total = (int64_t)ngroups * per;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t grp = i / per, r0 = i % per;
+        const int kx = (int)(r0 % nxh);
+        const int iy = (int)((r0 / nxh) % ny), iz = (int)(r0 / ((int64_t)nxh * ny));
+        const int ky = k_of_pos(iy, ny), kz = k_of_pos(iz, nz);
+        cx<T>* v = spec + grp * 3 * per + r0;
+        cx<T> a = v[0], b = v[per], c = v[2 * per];
+        if (kx > g.Kx || ky > g.Ky || -ky > g.Ky || kz > g.K || -kz > g.K) {
+            a = b = c = {T(0), T(0)};
+        } else if (kx != 0 || ky != 0 || kz != 0) {
+            const T fx = T(g.ax) * T(kx), fy = T(g.ay) * T(ky), fz = T(g.az) * T(kz);
+            const T ik2 = T(1) / (fx * fx + fy * fy + fz * fz);
+            const T kr = (fx * a.x + fy * b.x + fz * c.x) * ik2, ki = (fx * a.y + fy * b.y + fz * c.y) * ik2;
+            a = {a.x - fx * kr, a.y - fx * ki};
+            b = {b.x - fy * kr, b.y - fy * ki};
+            c = {c.x - fz * kr, c.y - fz * ki};
+        }
+        v[0] = a;
+        v[per] = b;
+        v[2 * per] = c;
+    }
+}
+
+// Per group: partial sums of 1/2 w |v|^2 and 1/2 w |k|^2 |v|^2 (w = 1 on the
+// kx = 0 and kx = nx/2 planes, else 2) over blockIdx.x's share, fixed order.
+constexpr int PROJ_BLOCKS = 64;
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_quad_abi_part(const cx<T>* __restrict__ spec, Geo g,
+                                                               double* __restrict__ part) {
+    __shared__ double se[RED_THREADS], sz[RED_THREADS];
+    const int nx = g.nx, ny = g.ny, nz = g.n, nxh = nx / 2 + 1;
+    const int64_t per = (int64_t)nz * ny * nxh;
+    const cx<T>* base = spec + (int64_t)blockIdx.y * 3 * per;
+    double e = 0.0, z = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (int64_t)gridDim.x * blockDim.x) {
+        const int kx = (int)(i % nxh);
+        const int ky = k_of_pos((int)((i / nxh) % ny), ny), kz = k_of_pos((int)(i / ((int64_t)nxh * ny)), nz);
+        const double w = (kx == 0 || 2 * kx == nx) ? 0.5 : 1.0;
+        double q = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const cx<T> v = base[c * per + i];
+            q += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
+        const double fx = g.ax * kx, fy = g.ay * ky, fz = g.az * kz;
+        e += w * q;
+        z += w * (fx * fx + fy * fy + fz * fz) * q;
+    }
+    se[threadIdx.x] = e;
+    sz[threadIdx.x] = z;
+    __syncthreads();
+    for (int h = RED_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            se[threadIdx.x] += se[threadIdx.x + h];
+            sz[threadIdx.x] += sz[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * ((int64_t)blockIdx.y * PROJ_BLOCKS + blockIdx.x)] = se[0];
+        part[2 * ((int64_t)blockIdx.y * PROJ_BLOCKS + blockIdx.x) + 1] = sz[0];
+    }
+}
+
+__global__ void k_quad_abi_final(const double* __restrict__ part, double* __restrict__ out) {
+    // one thread per (group, quantity): the PROJ_BLOCKS partials in order
+    const int grp = blockIdx.x, q = threadIdx.x;
+    if (q > 1) return;
+    double s = 0.0;
+    for (int b = 0; b < PROJ_BLOCKS; ++b) s += part[2 * (grp * PROJ_BLOCKS + b) + q];
+    out[2 * grp + q] = s;
+}
+
+template <typename T>
+static void launch_project(pst_plan* P, void* spec, int ngroups, double* part, double* res) {
+    KTimer tm(P, PST_K_OTHER);
+    const int64_t tot = (int64_t)ngroups * (abi_spec_bytes(P, 1) / P->esz);
+    hipLaunchKernelGGL((k_project_abi<T>), dim3(grid_for(tot)), dim3(256), 0, P->stream, (cx<T>*)spec, P->geo, ngroups);
+    if (part) {
+        hipLaunchKernelGGL((k_quad_abi_part<T>), dim3(PROJ_BLOCKS, ngroups), dim3(RED_THREADS), 0, P->stream,
+                           (const cx<T>*)spec, P->geo, part);
+        hipLaunchKernelGGL(k_quad_abi_final, dim3(ngroups), dim3(64), 0, P->stream, part, res);
+    }
+}
+
+extern "C" pst_status pst_project(pst_plan* P, void* spec_dev, int ngroups, double* energy, double* enstrophy) {
+    if (!P) return PST_ERR_INVALID_ARG;
+    if (!spec_dev) return fail(P, PST_ERR_INVALID_ARG, "NULL buffer");
+    if (ngroups < 1) return fail(P, PST_ERR_INVALID_ARG, "ngroups < 1");
+    if (P->geo.full) return fail(P, PST_ERR_UNSUPPORTED, "projection of a complex field");
+    const bool diag = energy || enstrophy;
+    double* part = nullptr;
+    if (diag) {
+        // partials and results after any other scratch of the plan's spectral buffer
+        const size_t need = sizeof(double) * (size_t)ngroups * (2 * PROJ_BLOCKS + 2);
+        pst_status s = ensure_abi(P, need);
+        if (s) return s;
+        part = (double*)P->abi;
+    }
+    double* res = part ? part + 2 * (size_t)ngroups * PROJ_BLOCKS : nullptr;
+    if (P->p.precision == PST_FP64) launch_project<double>(P, spec_dev, ngroups, part, res);
+    else launch_project<float>(P, spec_dev, ngroups, part, res);
+    pst_status s = check_launch(P, "project");
+    if (s || !diag) return s;
+    std::vector<double> h(2 * (size_t)ngroups);
+    HIPCHK(P, hipMemcpyAsync(h.data(), res, sizeof(double) * h.size(), hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(P, hipStreamSynchronize(P->stream));
+    for (int i = 0; i < ngroups; ++i) {
+        if (energy) energy[i] = h[2 * i];
+        if (enstrophy) enstrophy[i] = h[2 * i + 1];
+        if (!isfinite(h[2 * i]) || !isfinite(h[2 * i + 1])) return fail(P, PST_ERR_NONFINITE, "group %d", i);
+    }
+    return PST_OK;
+}
+
 extern "C" pst_status pst_energy(pst_plan* P, double out[2]) { return quadratic_diag(P, out, 0, "energy"); }
 
 extern "C" pst_status pst_enstrophy(pst_plan* P, double out[2]) { return quadratic_diag(P, out, 1, "enstrophy"); }

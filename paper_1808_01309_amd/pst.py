@@ -79,6 +79,8 @@ for _name, _args in [("pst_set_state", [_P, _I, _I, _P, _I]), ("pst_get_state", 
     getattr(lib, _name).argtypes = _args
     getattr(lib, _name).restype = _S
 
+lib.pst_project.argtypes = [_P, _P, _I, _P, _P]
+lib.pst_project.restype = _S
 lib.pst_fft_c2r_noalloc.argtypes = [_I, _I, _P, _P, _I, _P]
 lib.pst_fft_c2r_noalloc.restype = _S
 lib.pst_fft_c2r_noalloc_bytes.argtypes = [_I, _I, _I]
@@ -131,7 +133,7 @@ EXPORTED = ["pst_fno_create", "pst_fno_destroy", "pst_fno_last_error", "pst_fno_
             "pst_status_str", "pst_last_error", "pst_supported_n", "pst_plan_create", "pst_plan_destroy",
             "pst_set_state", "pst_get_state", "pst_set_forcing", "pst_rhs", "pst_step", "pst_energy", "pst_enstrophy",
             "pst_spectrum", "pst_fft_r2c", "pst_fft_c2r", "pst_query", "pst_timer_read",
-            "pst_fft_c2r_noalloc", "pst_fft_c2r_noalloc_bytes"]
+            "pst_fft_c2r_noalloc", "pst_fft_c2r_noalloc_bytes", "pst_project"]
 
 
 class PstError(RuntimeError):
@@ -345,6 +347,19 @@ class Plan:
         a, _ = _ptr(x)
         b, _ = _ptr(out)
         self._check(lib.pst_fft_c2r(self._h, a, b, nfields))
+
+    def project(self, spec_dev, ngroups, diagnostics=True):
+        """Dealias and project ngroups 3-component spectral fields in place
+        (device [ngroups][3][nz][ny][nx/2+1]); with diagnostics, returns the
+        energy and enstrophy of every group (numpy arrays)."""
+        _check_buf(spec_dev, self.cplx_np, ngroups * int(np.prod(self.spec_shape(3))), "project", device=True)
+        if not diagnostics:
+            self._check(lib.pst_project(self._h, _ptr(spec_dev)[0], ngroups, None, None))
+            return None
+        e = np.zeros(ngroups, np.float64)
+        z = np.zeros(ngroups, np.float64)
+        self._check(lib.pst_project(self._h, _ptr(spec_dev)[0], ngroups, e.ctypes.data_as(_P), z.ctypes.data_as(_P)))
+        return e, z
 
     def query(self):
         info = pst_info()

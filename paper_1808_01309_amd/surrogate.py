@@ -132,6 +132,7 @@ def rollout(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4, tol=1e-
     sol = _Stage(sizes, nu, dt, rk, conv)     # solver windows and audits
     x = init_phys.clone()
     y = torch.empty_like(x)
+    spec_sur = torch.empty_like(conv.spec)   # the surrogate's output, projected, in spectral space
     stats = {"apps": apps, "horizon": horizon, "guard_fail": 0, "audits": 0, "audit_fail": 0,
              "solver_windows": 0, "audit_err": []}
     # per window: wall time since the start, who advanced it, and the state
@@ -159,8 +160,10 @@ def rollout(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4, tol=1e-
                 states.append(x.clone())
             continue
         fno.forward(x, y)
-        sur.load(y, project=True)
-        e1, z1 = sur.ens.diagnostics()
+        # dealias + projection of all runs in one call, with their energy and
+        # enstrophy (the guard's inputs)
+        conv.to_spec(y, spec_sur, 3 * B)
+        e1, z1 = conv.plan.project(spec_sur, B)
         e_pred = e_in * np.exp(-2.0 * nu * z_in / e_in * horizon * dt)
         guard_ok = bool(np.all(np.abs(e1 - e_pred) <= tau_e * e_pred))
         audit = (a % audit_every) == audit_every - 1
@@ -168,6 +171,8 @@ def rollout(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4, tol=1e-
             if not sol_has_x:
                 sol.load(x)
             sol.ens.step(horizon)
+            for b in range(B):
+                sur.ens.set_state(b, spec_sur[b])
             err = sur.ens.rel_l2(sol.ens)
             if audit:
                 stats["audits"] += 1
@@ -186,7 +191,7 @@ def rollout(fno, init_phys, apps=50, horizon=10, nu=1e-2, dt=1e-3, rk=4, tol=1e-
                 if reference:
                     states.append(x.clone())
                 continue
-        sur.store(x)
+        conv.to_phys(spec_sur, x, 3 * B)
         e_in, z_in = e1, z1
         sol_has_x = False
         t_win.append(time.perf_counter() - t0)
