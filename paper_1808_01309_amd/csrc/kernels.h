@@ -654,8 +654,7 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
     // kx^2 + ky^2: uniform over a wavefront when a line fills whole
     // wavefronts (G >= 64), so its table entries come through scalar loads
     // into scalar registers
-    int kp2 = kx * kx + iky * iky;
-    if constexpr (G >= 64) kp2 = __builtin_amdgcn_readfirstlane(kp2);
+    const int kp2 = G >= 64 ? __builtin_amdgcn_readfirstlane(kx * kx + iky * iky) : 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int q = F::last_pos(g, e);
@@ -687,19 +686,24 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
             for (int c = 0; c < 3; ++c) o[c] = cadd(o[c], ra.F[c * fs + fi]);
         }
         if (ra.lin_only) o[0] = o[1] = o[2] = czero<T>();
-        // integrating factors: on the 2 pi box the product of the tables at
-        // kx^2 + ky^2 (one entry per line) and at kz^2 (the same few entries
-        // for every line), exp(-c |k|^2) = exp(-c k_perp^2) exp(-c kz^2): a
-        // direct lookup by |k|^2 scatters over the whole table, which at
-        // n = 1024 (1.4 MB per table) L2 does not keep and fetched again
-        // (1.55x the algorithmic bytes of the MHD pass); on other boxes
-        // exp(-visc |k|^2 h / 2) evaluated here in FP64 and rounded once.
-        // Loaded once per mode for all components (the stage-array stores in
-        // between would otherwise force reloads).
+        // integrating factors: on the 2 pi box, for lines of whole
+        // wavefronts (n >= 512), the product of the tables at kx^2 + ky^2
+        // (one scalar load per line) and at kz^2 (the same few entries for
+        // every line), exp(-c |k|^2) = exp(-c k_perp^2) exp(-c kz^2): a direct
+        // lookup by |k|^2 scatters over the whole table, which at n = 1024
+        // (1.4 MB per table) L2 does not keep and fetched again (1.55x the
+        // algorithmic bytes of the MHD pass); smaller grids, whose tables stay
+        // in cache, look up |k|^2 directly; on other boxes exp(-visc |k|^2 h / 2)
+        // is evaluated here in FP64 and rounded once.  Loaded once per mode for
+        // all components (the stage-array stores in between would otherwise
+        // force reloads).
         T Eu, E2u;
-        if constexpr (!ANI) {
+        if constexpr (!ANI && G >= 64) {
             Eu = ra.E[0][kp2] * ra.E[0][ikz * ikz];
             E2u = ra.E2[0][kp2] * ra.E2[0][ikz * ikz];
+        } else if constexpr (!ANI) {
+            Eu = ra.E[0][k2];
+            E2u = ra.E2[0][k2];
         } else {
             const double eu = exp(-0.5 * ra.visc[0] * ra.hd * (kxy2 + geo.az * geo.az * ikz * ikz));
             Eu = T(eu);
@@ -707,9 +711,12 @@ __device__ __forceinline__ void zfwd_lines(const cx<T>* __restrict__ D, const cx
         }
         // the second group's factors (b, theta), loaded where they are used
         auto second_if = [&](T& Eb, T& E2b) {
-            if constexpr (!ANI) {
+            if constexpr (!ANI && G >= 64) {
                 Eb = ra.E[1][kp2] * ra.E[1][ikz * ikz];
                 E2b = ra.E2[1][kp2] * ra.E2[1][ikz * ikz];
+            } else if constexpr (!ANI) {
+                Eb = ra.E[1][k2];
+                E2b = ra.E2[1][k2];
             } else {
                 const double eb = exp(-0.5 * ra.visc[1] * ra.hd * (kxy2 + geo.az * geo.az * ikz * ikz));
                 Eb = T(eb);
