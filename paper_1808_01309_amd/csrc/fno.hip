@@ -6,7 +6,8 @@
 //   K_l(v) = c2r(R_l . r2c(v) on the retained modes).
 //
 // Channel mixing (every dense layer, forward and backward) is a GEMM over
-// points on the matrix cores: v_mfma_f32_32x32x8_bf16 with BF16 weights and
+// points on the matrix cores: v_mfma_f32_32x32x16_bf16 (forward) and
+// v_mfma_f32_32x32x8_bf16 (weight gradients) with BF16 weights and
 // activations and FP32 accumulation (an FP32 FMA variant of the same kernels
 // exists for gradient checks).  The spectral layers run the library's own 3D
 // r2c / c2r transform kernels; the per-mode complex channel mixing and its
@@ -34,9 +35,10 @@ enum { EPI_NONE = 0, EPI_GELU = 1, EPI_DGELU = 2 };
 
 // out[b][o][p] = epi( sum_k W[o][k] X'[b][k][p] + bias[o] + add[b][o][p] ),
 // X' = gelu(X) if GELU_IN.  One wave computes 32 points x 32 output channels
-// (output tile blockIdx.y); the K loop steps by 8 (one MFMA).
-//   MFMA operands (32x32x8): A[m][k] lane m + 32 (k / 4), element k % 4;
-//   B[k][n] lane n + 32 (k / 4); D[m][n] lane n + 32 ((m / 4) % 2),
+// (output tile blockIdx.y); the K loop steps by 16 (one MFMA, gfx950's
+// 32x32x16 BF16 form; Kpad is a multiple of 16).
+//   MFMA operands: A[m][k] lane m + 32 ((k / 8) % 2), element k % 8 of step
+//   k / 16; B[k][n] lane n + 32 ((k / 8) % 2); D[m][n] lane n + 32 ((m / 4) % 2),
 //   register (m % 4) + 4 (m / 8).
 template <bool MFMA, bool GELU_IN, int EPI>
 __global__ __launch_bounds__(GT) void k_gemm(const unsigned short* __restrict__ Wb, const float* __restrict__ Wf,
@@ -55,18 +57,18 @@ __global__ __launch_bounds__(GT) void k_gemm(const unsigned short* __restrict__ 
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
     if constexpr (MFMA) {
-        const unsigned short* wrow = Wb + (int64_t)(ot * 32 + n) * Kpad + 4 * kg;
-        for (int s = 0; s < Kpad / 8; ++s) {
-            bf16x4 bb, aa;
+        const unsigned short* wrow = Wb + (int64_t)(ot * 32 + n) * Kpad + 8 * kg;
+        for (int s = 0; s < Kpad / 16; ++s) {
+            bf16x8v bb;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = 8 * s + 4 * kg + j;
+            for (int j = 0; j < 8; ++j) {
+                const int k = 16 * s + 8 * kg + j;
                 float x = k < K ? Xb[(int64_t)k * P] : 0.f;
                 if (GELU_IN) x = gelu_f(x);
-                bb[j] = (short)f2bf(x);
-                aa[j] = (short)wrow[8 * s + j];
+                bb[j] = (__bf16)x;
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aa, bb, acc, 0, 0, 0);
+            const bf16x8v aa = *(const bf16x8v*)(wrow + 16 * s);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa, bb, acc, 0, 0, 0);
         }
     } else {
         for (int k = 0; k < K; ++k) {
@@ -201,16 +203,18 @@ __global__ void k_bgrad_reduce(const double* __restrict__ part, int O, float* __
 // forward spectral mixing on compact spectra [b][c][mode] (mode stride 1,
 // channel stride nm): out[b][o][m] = sum_c R[m][c][o] V[b][c][m].  A block
 // takes MB consecutive modes so that every (b, c) row is read and written as
-// one contiguous MB-element segment; the modes' slices meet in LDS, and each
-// mode's weight matrix is staged there (coalesced) before it is used.
-//   LDS: Vh [MB][B C], Out [MB][B O], Rs [C][O]
+// one contiguous MB-element segment; the modes' slices meet in LDS.  A thread
+// owns one (mode, o) and accumulates 8 batch entries at a time: the weights
+// R[m][c][o] are read straight from memory (consecutive o in consecutive
+// lanes), the spectra from LDS (the lanes of a wavefront read a few addresses:
+// broadcasts).
+//   LDS: Vh [MB][B C], Out [MB][B O]
 __global__ __launch_bounds__(GT) void k_mix_fwd(const cx<float>* __restrict__ spec_in, const cx<float>* __restrict__ R,
                                                 int nm, int MB, int B, int C, int O, cx<float>* __restrict__ spec_out,
                                                 cx<float>* __restrict__ vstore) {
     extern __shared__ cx<float> shm[];
     cx<float>* Vh = shm;
     cx<float>* Out = Vh + MB * B * C;
-    cx<float>* Rs = Out + MB * B * O;
     const int m0 = blockIdx.x * MB;
     const int mb = nm - m0 < MB ? nm - m0 : MB;
     for (int q = threadIdx.x; q < B * C * MB; q += GT) {
@@ -220,23 +224,33 @@ __global__ __launch_bounds__(GT) void k_mix_fwd(const cx<float>* __restrict__ sp
         Vh[mm * B * C + i] = v;
         if (vstore) vstore[(int64_t)(m0 + mm) * B * C + i] = v;
     }
-    for (int mm = 0; mm < mb; ++mm) {
-        const cx<float>* Rm = R + (int64_t)(m0 + mm) * C * O;
-        for (int j = threadIdx.x; j < C * O; j += GT) Rs[j] = Rm[j];
-        __syncthreads();
+    __syncthreads();
+    constexpr int BB = 8;
+    for (int t = threadIdx.x; t < mb * O; t += GT) {
+        const int mm = t / O, o = t % O;
+        const cx<float>* Rm = R + (int64_t)(m0 + mm) * C * O + o;
         const cx<float>* V = Vh + mm * B * C;
-        for (int i = threadIdx.x; i < B * O; i += GT) {
-            const int b = i / O, o = i % O;
-            float re = 0.f, im = 0.f;
+        for (int b0 = 0; b0 < B; b0 += BB) {
+            cx<float> acc[BB];
+#pragma unroll
+            for (int bb = 0; bb < BB; ++bb) acc[bb] = czero<float>();
+#pragma unroll 8
             for (int c = 0; c < C; ++c) {
-                const cx<float> r = Rs[c * O + o], v = V[b * C + c];
-                re += r.x * v.x - r.y * v.y;
-                im += r.x * v.y + r.y * v.x;
+                const cx<float> r = Rm[(int64_t)c * O];
+#pragma unroll
+                for (int bb = 0; bb < BB; ++bb) {
+                    if (b0 + bb >= B) break;
+                    const cx<float> v = V[(b0 + bb) * C + c];
+                    acc[bb].x += r.x * v.x - r.y * v.y;
+                    acc[bb].y += r.x * v.y + r.y * v.x;
+                }
             }
-            Out[mm * B * O + i] = {re, im};
+#pragma unroll
+            for (int bb = 0; bb < BB; ++bb)
+                if (b0 + bb < B) Out[mm * B * O + (b0 + bb) * O + o] = acc[bb];
         }
-        __syncthreads();  // Rs is rewritten by the next mode
     }
+    __syncthreads();
     for (int q = threadIdx.x; q < B * O * MB; q += GT) {
         const int i = q / MB, mm = q % MB;
         if (mm < mb) spec_out[(int64_t)i * nm + m0 + mm] = Out[mm * B * O + i];
@@ -346,7 +360,7 @@ __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, floa
 }
 
 // padded copies of a dense weight [O][K] (at theta + off): W [Opad][Kpad] and
-// its transpose WT [Kpad'][Opad'] (Kpad' = roundup(K, 32), Opad' = roundup(O, 8)),
+// its transpose WT [Kpad'][Opad'] (Kpad' = roundup(K, 32), Opad' = roundup(O, 16)),
 // both as BF16 and FP32
 __global__ void k_pack(const float* __restrict__ w, int O, int K, int Opad, int Kpad, int Tpad_o, int Tpad_k,
                        unsigned short* __restrict__ Wb, float* __restrict__ Wf, unsigned short* __restrict__ Tb,
@@ -398,7 +412,7 @@ extern "C" void pst_fno_destroy(pst_fno* F) {
     hipStreamSynchronize(F->stream);
     std::vector<void*> bufs = {F->theta, F->grad, F->am, F->av, F->modeoff, F->modew, F->v, F->s, F->kb, F->pre,
                                F->out, F->dv, F->ds, F->dpre, F->dout, F->tmp, F->specA, F->specB, F->ffttmp,
-                               F->vst, F->part, F->lpart, F->coef};
+                               F->vst, F->part, F->lpart, F->coef, F->fact};
     FnoDense* ds[] = {&F->lift, &F->q1, &F->q2};
     for (FnoDense* d : ds)
         for (void* b : {(void*)d->Wb, (void*)d->Tb, (void*)d->Wf, (void*)d->Tf}) bufs.push_back(b);
@@ -423,9 +437,9 @@ static bool make_dense(FnoDense& d, int O, int K, int64_t off) {
     d.O = O;
     d.K = K;
     d.Opad = rup(O, 32);
-    d.Kpad = rup(K, 8);
+    d.Kpad = rup(K, 16);
     d.To = rup(K, 32);
-    d.Tk = rup(O, 8);
+    d.Tk = rup(O, 16);
     d.off = off;
     return dmalloc((void**)&d.Wb, sizeof(unsigned short) * d.Opad * d.Kpad) &&
            dmalloc((void**)&d.Wf, sizeof(float) * d.Opad * d.Kpad) &&
@@ -500,6 +514,10 @@ extern "C" pst_status pst_fno_create(const pst_fno_params* p, void* hip_stream, 
          dmalloc((void**)&F->ffttmp, 8 * wsp) && dmalloc((void**)&F->vst, 8 * (int64_t)L * F->nm * B * W) &&
          dmalloc((void**)&F->part, 4 * F->wpart_floats) && dmalloc((void**)&F->lpart, sizeof(double) * 2 * 64 * 1024) &&
          dmalloc((void**)&F->coef, sizeof(float) * 64);
+    // fused inference activations: two slots, point-major with the padded channel stride
+    F->fact_slot = (int64_t)B * F->P * fno_act_cp(W, p->mfma != 0) * (p->mfma ? 2 : 4);
+    F->fact_slot = (F->fact_slot + 255) / 256 * 256;
+    ok = ok && (!fno_fused_supported(n) || dmalloc(&F->fact, 2 * (size_t)F->fact_slot));
     if (!ok) {
         g_fno_err = "device allocation failed";
         pst_fno_destroy(F);
@@ -623,13 +641,14 @@ static void dense_grad(pst_fno* F, const FnoDense& d, const float* Y, const floa
                        F->grad + d.off + (int64_t)d.O * d.K);
 }
 
-// forward spectral mixing launch: MB modes per block, LDS (2 MB B W + W W
-// complex) <= 64 KB for every admissible batch and width
+// forward spectral mixing launch: MB modes per block (8 at batch 8, width 32:
+// one (mode, o) per thread), LDS 2 MB B W complex <= 32 KB for every
+// admissible batch and width
 static void mix_fwd(pst_fno* F, int l, int B, cx<float>* vstore) {
     const int W = F->p.width;
     int MB = 2048 / (B * W);
     MB = MB < 1 ? 1 : (MB > 8 ? 8 : MB);
-    const size_t sh = sizeof(cx<float>) * (2 * (size_t)MB * B * W + (size_t)W * W);
+    const size_t sh = sizeof(cx<float>) * (2 * (size_t)MB * B * W);
     hipLaunchKernelGGL(k_mix_fwd, dim3((F->nm + MB - 1) / MB), dim3(GT), sh, F->stream, F->specA,
                        (const cx<float>*)(F->theta + F->offR[l]), F->nm, MB, B, W, W, F->specB, vstore);
 }
@@ -664,12 +683,11 @@ static void forward_pass(pst_fno* F, const float* u, int B, float* out) {
 }
 
 // Inference forward on the fused layer kernels: activations ping-pong between
-// two slots of F->v (BF16 on the matrix-core path), the x-transformed lines of
-// the spectral branch stay in the transform workspace between kernels.
+// the two slots of F->fact (BF16 on the matrix-core path), the x-transformed
+// lines of the spectral branch stay in the transform workspace between kernels.
 static void forward_fused(pst_fno* F, const float* u, int B, float* out) {
     const int W = F->p.width, L = F->p.layers, m = F->p.modes;
-    const int64_t astride = (int64_t)F->p.batch * W * F->P;
-    void* act[2] = {F->v, F->v + astride};
+    void* act[2] = {F->fact, (char*)F->fact + F->fact_slot};
     fno_fused_lift(F, u, B, act[0], F->ffttmp);
     for (int l = 0; l < L; ++l) {
         F->fft->L->modes_yz_fwd(F->fft, F->specA, B * W, m, F->ffttmp);

@@ -14,9 +14,16 @@
 //
 // The first kernel applies the lift instead of a layer; the last fuses the
 // projection 32 -> hidden -> GELU -> 3 and the residual, so v_L and the hidden
-// activations never reach HBM.  Between layers the activations are stored in
-// BF16 on the matrix-core path (exactly the values its MFMA operands take) and
-// FP32 otherwise; the spectral branch always transforms the FP32 values.
+// activations never reach HBM.  Between layers the activations are stored
+// point-major, [b][point][channel] with the channels padded to a multiple of
+// 16 (zeros), in BF16 on the matrix-core path (exactly the values its MFMA
+// operands take: each lane's eight consecutive channels are one 16-byte
+// load) and FP32 otherwise; they are written from LDS after the epilogue,
+// eight channels of a point per lane, so that a wavefront stores whole points
+// contiguously.  The spectral branch always transforms the FP32 values.  The matrix-core
+// path uses gfx950's v_mfma_f32_32x32x16_bf16 (K = 16 per instruction), and
+// its activation operands are loaded before the spectral branch's transform,
+// so that their latency overlaps it.
 #include "fno_internal.h"
 #include "kernels.h"
 
@@ -30,22 +37,25 @@ template <int N> constexpr int fno_rows() { return N <= 16 ? 8 : (N <= 32 ? 4 : 
 
 template <bool BF> struct Act;
 template <> struct Act<true> {
-    using T = unsigned short;
-    __device__ __forceinline__ static void st(T* p, int64_t i, float x) { p[i] = f2bf(x); }
+    using T = __bf16;
 };
 template <> struct Act<false> {
     using T = float;
-    __device__ __forceinline__ static void st(T* p, int64_t i, float x) { p[i] = x; }
 };
 
-// bytes of dynamic LDS: X [W][RB n] floats, then one FFT line scratch per pair slot
+// X, the block's values in LDS: channel c's RB rows at X[c PXS + r n + x].  The
+// row stride PXS = RB n + 1 puts the channels of one point on distinct banks
+// (the activation store phase reads 8 channels of a point per lane).
+template <int N> constexpr int xstride() { return fno_rows<N>() * N + 1; }
+// floats of X, rounded up so that the FFT line scratch after it is 8-byte aligned
+template <int N> __host__ __device__ constexpr int xfloats(int W) { return (W * xstride<N>() + 1) / 2 * 2; }
+// bytes of dynamic LDS: X, then one FFT line scratch per pair slot
 template <int N> size_t fused_lds(int W) {
-    return sizeof(float) * (size_t)W * fno_rows<N>() * N +
-           sizeof(cx<float>) * (size_t)(FT / NCfg<N>::G) * LineLds<float>::size(N);
+    return sizeof(float) * (size_t)xfloats<N>(W) + sizeof(cx<float>) * (size_t)(FT / NCfg<N>::G) * LineLds<float>::size(N);
 }
 
 // Block geometry: blockIdx.x = (b N + z) (N / RB) + yb, first point p0 of the
-// block in a field; the block's lines (row r, channel c) live at X[c][r N + x].
+// block in a field; the block's lines (row r, channel c) live at X[c PXS + r N + x].
 struct RowBlock {
     int b, z, y0;
     int64_t p0;
@@ -69,7 +79,7 @@ template <int N> __device__ __forceinline__ int64_t t1_line(const RowBlock& rb, 
 }
 template <int N> __device__ __forceinline__ int x_line(int l) {
     constexpr int RB = fno_rows<N>();
-    return (l / RB) * RB * N + (l % RB) * N;  // X[c][r N + x]
+    return (l / RB) * xstride<N>() + (l % RB) * N;  // X[c PXS + r N + x]
 }
 
 // x r2c of the block's RB W lines held in X, keeping kx < m, into t1.
@@ -154,43 +164,52 @@ __device__ __forceinline__ void rows_c2r(const cx<float>* __restrict__ t1, int W
 }
 
 // Channel mixing of one tile: acc[r] = sum_k W[ot 32 + m(r)][k] x[k][n] over
-// k < K for this lane's point n, in the MFMA 32x32x8 register layout
-// m(r) = 8 (r / 4) + 4 kg + r % 4.  x is a column of a channel-major array
-// (element stride xs).  K <= 64: at most 8 MFMA steps.
-constexpr int KS_MAX = 8;
+// k < K for this lane's point n, in the MFMA 32x32 register layout
+// m(r) = 8 (r / 4) + 4 kg + r % 4 (kg = lane / 32).  The 32x32x16 BF16 operands:
+// lane n + 32 kg holds A[m = n][k] and B[k][n] for k = 16 s + 8 kg + j,
+// j < 8, in K steps s (K <= 64: at most 4 steps).
+constexpr int KS_MAX = 4;
 struct BOps {
-    bf16x4 b[KS_MAX];
+    bf16x8v b[KS_MAX];
 };
-template <typename XT>
-__device__ __forceinline__ void load_bops(BOps& o, const XT* x, int64_t xs, int K, int Kpad, int kg) {
+// from stored BF16 activations of one point (channel-contiguous): one 16-byte load per step
+template <int KS>
+__device__ __forceinline__ void load_bops_act(BOps& o, const __bf16* __restrict__ x, int ks, int kg) {
 #pragma unroll
-    for (int s = 0; s < KS_MAX; ++s) {
-        if (s >= Kpad / 8) break;
+    for (int s = 0; s < KS; ++s) {
+        if (s >= ks) break;
+        o.b[s] = *(const bf16x8v*)(x + 16 * s + 8 * kg);
+    }
+}
+// from FP32 values with channel stride xs (LDS); channels >= K read as zero
+template <int KS>
+__device__ __forceinline__ void load_bops_f32(BOps& o, const float* x, int64_t xs, int K, int ks, int kg) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int k = 8 * s + 4 * kg + j;
-            if constexpr (sizeof(XT) == 2) o.b[s][j] = k < K ? (short)x[k * xs] : (short)0;
-            else o.b[s][j] = k < K ? (short)f2bf(x[k * xs]) : (short)0;
+    for (int s = 0; s < KS; ++s) {
+        if (s >= ks) break;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 16 * s + 8 * kg + j;
+            o.b[s][j] = (__bf16)(k < K ? x[k * xs] : 0.f);
         }
     }
 }
-__device__ __forceinline__ f32x16 mfma_tile(const BOps& o, const unsigned short* __restrict__ Wb, int Kpad, int ot,
+template <int KS>
+__device__ __forceinline__ f32x16 mfma_tile(const BOps& o, const __bf16* __restrict__ Wb, int Kpad, int ks, int ot,
                                             int n, int kg) {
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    const unsigned short* wrow = Wb + (int64_t)(ot * 32 + n) * Kpad + 4 * kg;
+    const __bf16* wrow = Wb + (int64_t)(ot * 32 + n) * Kpad + 8 * kg;
 #pragma unroll
-    for (int s = 0; s < KS_MAX; ++s) {
-        if (s >= Kpad / 8) break;
-        bf16x4 aa;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) aa[j] = (short)wrow[8 * s + j];
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aa, o.b[s], acc, 0, 0, 0);
+    for (int s = 0; s < KS; ++s) {
+        if (s >= ks) break;
+        const bf16x8v a = *(const bf16x8v*)(wrow + 16 * s);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, o.b[s], acc, 0, 0, 0);
     }
     return acc;
 }
-// FP32 FMA variant, same register layout (W FP32 [.][Kpad])
+// FP32 FMA variant, same register layout (W FP32 [.][Kpad]; x[k xs] for k < K)
 __device__ __forceinline__ f32x16 fma_tile(const float* __restrict__ Wf, int Kpad, int K, int ot, const float* x,
                                            int64_t xs, int kg) {
     f32x16 acc;
@@ -204,54 +223,92 @@ __device__ __forceinline__ f32x16 fma_tile(const float* __restrict__ Wf, int Kpa
     return acc;
 }
 
+// Store the block's activations from X (FP32, after a barrier) to HBM,
+// point-major: a lane writes 8 consecutive channels of one point (16 bytes,
+// zeros past W), so that a wavefront's store covers whole points contiguously.
+template <int N, bool BF>
+__device__ __forceinline__ void store_act(const float* X, int W, typename Act<BF>::T* __restrict__ vb) {
+    constexpr int PB = fno_rows<N>() * N, PXS = xstride<N>();
+    if constexpr (BF) {
+        const int G8 = fno_act_cp(W, true) / 8;
+        for (int i = threadIdx.x; i < G8 * PB; i += FT) {
+            const int pt = i / G8, og = i % G8;
+            bf16x8v q;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int c = 8 * og + j;
+                q[j] = (__bf16)(c < W ? X[c * PXS + pt] : 0.f);
+            }
+            *(bf16x8v*)(vb + ((int64_t)pt * G8 + og) * 8) = q;
+        }
+    } else {
+        for (int i = threadIdx.x; i < W * PB; i += FT) {
+            const int pt = i / W, c = i % W;
+            vb[(int64_t)pt * W + c] = X[c * PXS + pt];
+        }
+    }
+}
+
 template <int N, bool BF>
 __global__ __launch_bounds__(FT) void k_fno_lift(const float* __restrict__ u, const float* __restrict__ Wl,
                                                  const float* __restrict__ bl, int W, int m,
                                                  typename Act<BF>::T* __restrict__ vout, cx<float>* __restrict__ t1,
                                                  const cx<float>* __restrict__ tw) {
-    constexpr int PB = fno_rows<N>() * N;
+    constexpr int PB = fno_rows<N>() * N, PXS = xstride<N>();
     constexpr int64_t P3 = (int64_t)N * N * N;
     extern __shared__ float X[];
-    cx<float>* fl = (cx<float>*)(X + W * PB);
+    cx<float>* fl = (cx<float>*)(X + xfloats<N>(W));
     const RowBlock rb = row_block<N>();
     const float* ub = u + (int64_t)rb.b * 3 * P3 + rb.p0;
+    const int CP = fno_act_cp(W, BF);
+    typename Act<BF>::T* vb = vout + ((int64_t)rb.b * P3 + rb.p0) * CP;
+    // consecutive threads take consecutive points (distinct LDS banks)
     for (int i = threadIdx.x; i < W * PB; i += FT) {
         const int o = i / PB, pt = i % PB;
-        const float s = bl[o] + Wl[3 * o] * ub[pt] + Wl[3 * o + 1] * ub[P3 + pt] + Wl[3 * o + 2] * ub[2 * P3 + pt];
-        X[i] = s;
-        Act<BF>::st(vout, ((int64_t)rb.b * W + o) * P3 + rb.p0 + pt, s);
+        X[o * PXS + pt] = bl[o] + Wl[3 * o] * ub[pt] + Wl[3 * o + 1] * ub[P3 + pt] + Wl[3 * o + 2] * ub[2 * P3 + pt];
     }
     __syncthreads();
+    store_act<N, BF>(X, W, vb);
     rows_r2c<N>(X, W, m, rb, t1, tw, fl);
 }
 
 struct ProjArgs {
-    const unsigned short* Wb;  // Wq1 padded [Hpad][Kpad] BF16
-    const float* Wf;           // same, FP32
+    const __bf16* Wb;  // Wq1 padded [Hpad][Kpad] BF16
+    const float* Wf;   // same, FP32
     int Kpad, H, Hpad;
     const float *bq1, *Wq2, *bq2;  // Wq2 [3][H]
     const float* u;
     float* out;
 };
 
-template <int N, bool BF, bool LAST>
+// KS: MFMA K steps compiled for (2: K <= 32, 4: K <= 64); ks = Kpad / 16 at run time.
+template <int N, bool BF, bool LAST, int KS>
 __global__ __launch_bounds__(FT) void k_fno_layer(const typename Act<BF>::T* __restrict__ vin,
-                                                  const unsigned short* __restrict__ Wb, const float* __restrict__ Wf,
+                                                  const __bf16* __restrict__ Wb, const float* __restrict__ Wf,
                                                   int Kpad, int Opad, const float* __restrict__ bias, int W, int m,
                                                   typename Act<BF>::T* __restrict__ vout, cx<float>* __restrict__ t1,
                                                   const cx<float>* __restrict__ tw, ProjArgs pa) {
-    constexpr int PB = fno_rows<N>() * N, PT = PB / 32;
+    constexpr int PB = fno_rows<N>() * N, PT = PB / 32, PXS = xstride<N>();
     constexpr int64_t P3 = (int64_t)N * N * N;
+    static_assert(PT <= FT / 64, "one 32-point tile per wavefront");
     static_assert(sizeof(float) * 4 * 256 <= sizeof(cx<float>) * (FT / NCfg<N>::G) * LineLds<float>::size(N),
                   "projection weights (hidden <= 256) must fit in the FFT scratch");
     extern __shared__ float X[];
-    cx<float>* fl = (cx<float>*)(X + W * PB);
+    cx<float>* fl = (cx<float>*)(X + xfloats<N>(W));
     const RowBlock rb = row_block<N>();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n = lane & 31, kg = lane >> 5;
+    const int CP = fno_act_cp(W, BF), ks = Kpad / 16;
+    // this wavefront's tile: points pt0 .. pt0 + 31 of the block, every output channel
+    const bool tile = wave < PT;
+    const int pt0 = wave * 32;
+    const int64_t gp = (int64_t)rb.b * P3 + rb.p0 + pt0 + n;   // this lane's point
+    const typename Act<BF>::T* vp = vin + gp * CP;
 
-    const typename Act<BF>::T* vb = vin + (int64_t)rb.b * W * P3 + rb.p0 + n;
-    const int ntile = (Opad / 32) * PT;
-
+    // the mixing's activation operands, in flight while the spectral branch is transformed
+    BOps ops;
+    if constexpr (BF) {
+        if (tile) load_bops_act<KS>(ops, vp, ks, kg);
+    }
 
     // spectral branch of every line of the block
     rows_c2r<N>(t1, W, m, rb, X, tw, fl);
@@ -263,68 +320,61 @@ __global__ __launch_bounds__(FT) void k_fno_layer(const typename Act<BF>::T* __r
     }
 
     // channel mixing + bias + spectral branch (+ GELU), tiles of 32 channels x 32 points
-    for (int t = wave; t < ntile; t += FT / 64) {
-        const int ot = t / PT, pt0 = (t % PT) * 32;
-        f32x16 acc;
-        if constexpr (BF) {
-            BOps ops;
-            load_bops(ops, vb + pt0, P3, W, Kpad, kg);
-            acc = mfma_tile(ops, Wb, Kpad, ot, n, kg);
-        } else {
-            acc = fma_tile(Wf, Kpad, W, ot, vb + pt0, P3, kg);
-        }
+    if (tile) {
+        for (int ot = 0; ot < Opad / 32; ++ot) {
+            f32x16 acc;
+            if constexpr (BF) acc = mfma_tile<KS>(ops, Wb, Kpad, ks, ot, n, kg);
+            else acc = fma_tile(Wf, Kpad, W, ot, vp, 1, kg);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int o = ot * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
-            if (o >= W) continue;
-            float* xo = X + o * PB + pt0 + n;
-            float s = acc[r] + bias[o] + *xo;
-            if (!LAST) {
-                s = gelu_f(s);
-                Act<BF>::st(vout, ((int64_t)rb.b * W + o) * P3 + rb.p0 + pt0 + n, s);
+            for (int i = 0; i < 4; ++i) {
+                const int o0 = ot * 32 + 8 * i + 4 * kg;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int o = o0 + j;
+                    if (o < W) {
+                        float* xo = X + o * PXS + pt0 + n;
+                        float s = acc[4 * i + j] + bias[o] + *xo;
+                        if (!LAST) s = gelu_f(s);
+                        *xo = s;  // this lane is the only reader and writer of X[o][pt]
+                    }
+                }
             }
-            *xo = s;  // this lane is the only reader and writer of X[o][pt]
         }
     }
     __syncthreads();
 
     if constexpr (!LAST) {
+        store_act<N, BF>(X, W, vout + ((int64_t)rb.b * P3 + rb.p0) * CP);
         rows_r2c<N>(X, W, m, rb, t1, tw, fl);
-    } else {
-        // projection out = u + Wq2 gelu(Wq1 v + bq1) + bq2, one 32-point tile
-        // per wave; bq1 and Wq2 were staged in LDS (the FFT scratch).
-        for (int t = wave; t < PT; t += FT / 64) {
-            const int pt0 = t * 32;
-            float y0 = 0.f, y1 = 0.f, y2 = 0.f;
-            for (int ht = 0; ht < pa.Hpad / 32; ++ht) {
-                f32x16 acc;
-                if constexpr (BF) {
-                    BOps ops;
-                    load_bops(ops, X + pt0 + n, (int64_t)PB, W, pa.Kpad, kg);
-                    acc = mfma_tile(ops, pa.Wb, pa.Kpad, ht, n, kg);
-                } else {
-                    acc = fma_tile(pa.Wf, pa.Kpad, W, ht, X + pt0 + n, (int64_t)PB, kg);
-                }
+    } else if (tile) {
+        // projection out = u + Wq2 gelu(Wq1 v + bq1) + bq2 on this wave's tile;
+        // bq1 and Wq2 were staged in LDS (the FFT scratch)
+        BOps pops;
+        if constexpr (BF) load_bops_f32<KS>(pops, X + pt0 + n, (int64_t)PXS, W, pa.Kpad / 16, kg);
+        float y0 = 0.f, y1 = 0.f, y2 = 0.f;
+        for (int ht = 0; ht < pa.Hpad / 32; ++ht) {
+            f32x16 acc;
+            if constexpr (BF) acc = mfma_tile<KS>(pops, pa.Wb, pa.Kpad, pa.Kpad / 16, ht, n, kg);
+            else acc = fma_tile(pa.Wf, pa.Kpad, W, ht, X + pt0 + n, (int64_t)PXS, kg);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int h = ht * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
-                    if (h >= pa.H) continue;
-                    const float a = gelu_f(acc[r] + wl[h]);
-                    y0 += wl[pa.H + h] * a;
-                    y1 += wl[2 * pa.H + h] * a;
-                    y2 += wl[3 * pa.H + h] * a;
-                }
+            for (int r = 0; r < 16; ++r) {
+                const int h = ht * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
+                if (h >= pa.H) continue;
+                const float a = gelu_f(acc[r] + wl[h]);
+                y0 += wl[pa.H + h] * a;
+                y1 += wl[2 * pa.H + h] * a;
+                y2 += wl[3 * pa.H + h] * a;
             }
-            // the two half-waves hold disjoint hidden units of the same points
-            y0 += __shfl_xor(y0, 32);
-            y1 += __shfl_xor(y1, 32);
-            y2 += __shfl_xor(y2, 32);
-            if (kg == 0) {
-                const int64_t i0 = (int64_t)rb.b * 3 * P3 + rb.p0 + pt0 + n;
-                pa.out[i0] = pa.u[i0] + y0 + pa.bq2[0];
-                pa.out[i0 + P3] = pa.u[i0 + P3] + y1 + pa.bq2[1];
-                pa.out[i0 + 2 * P3] = pa.u[i0 + 2 * P3] + y2 + pa.bq2[2];
-            }
+        }
+        // the two half-waves hold disjoint hidden units of the same points
+        y0 += __shfl_xor(y0, 32);
+        y1 += __shfl_xor(y1, 32);
+        y2 += __shfl_xor(y2, 32);
+        if (kg == 0) {
+            const int64_t i0 = (int64_t)rb.b * 3 * P3 + rb.p0 + pt0 + n;
+            pa.out[i0] = pa.u[i0] + y0 + pa.bq2[0];
+            pa.out[i0 + P3] = pa.u[i0 + P3] + y1 + pa.bq2[1];
+            pa.out[i0 + 2 * P3] = pa.u[i0 + 2 * P3] + y2 + pa.bq2[2];
         }
     }
 }
@@ -338,14 +388,26 @@ struct Fused {
         const cx<float>* tw = (const cx<float>*)F->fft->tw;
         if (F->p.mfma)
             hipLaunchKernelGGL((k_fno_lift<N, true>), dim3(grid(B)), dim3(FT), fused_lds<N>(W), F->stream, u, Wl,
-                               Wl + 3 * W, W, F->p.modes, (unsigned short*)act, t1, tw);
+                               Wl + 3 * W, W, F->p.modes, (__bf16*)act, t1, tw);
         else
             hipLaunchKernelGGL((k_fno_lift<N, false>), dim3(grid(B)), dim3(FT), fused_lds<N>(W), F->stream, u, Wl,
                                Wl + 3 * W, W, F->p.modes, (float*)act, t1, tw);
     }
+    template <bool LAST, int KS>
+    static void layer_ks(pst_fno* F, const FnoDense& d, const float* bias, int B, const void* ain, void* aout,
+                         cx<float>* t1, const cx<float>* tw, const ProjArgs& pa) {
+        const int W = F->p.width;
+        if (F->p.mfma)
+            hipLaunchKernelGGL((k_fno_layer<N, true, LAST, KS>), dim3(grid(B)), dim3(FT), fused_lds<N>(W), F->stream,
+                               (const __bf16*)ain, (const __bf16*)d.Wb, d.Wf, d.Kpad, d.Opad, bias, W, F->p.modes,
+                               (__bf16*)aout, t1, tw, pa);
+        else
+            hipLaunchKernelGGL((k_fno_layer<N, false, LAST, KS>), dim3(grid(B)), dim3(FT), fused_lds<N>(W),
+                               F->stream, (const float*)ain, (const __bf16*)d.Wb, d.Wf, d.Kpad, d.Opad, bias, W,
+                               F->p.modes, (float*)aout, t1, tw, pa);
+    }
     template <bool LAST>
     static void layer(pst_fno* F, int l, int B, const void* ain, void* aout, cx<float>* t1, const float* u, float* out) {
-        const int W = F->p.width;
         const FnoDense& d = F->wc[l];
         const float* bias = F->theta + d.off + (int64_t)d.O * d.K;
         const cx<float>* tw = (const cx<float>*)F->fft->tw;
@@ -353,7 +415,7 @@ struct Fused {
         if (LAST) {
             const FnoDense& q1 = F->q1;
             const FnoDense& q2 = F->q2;
-            pa.Wb = q1.Wb;
+            pa.Wb = (const __bf16*)q1.Wb;
             pa.Wf = q1.Wf;
             pa.Kpad = q1.Kpad;
             pa.H = q1.O;
@@ -364,14 +426,9 @@ struct Fused {
             pa.u = u;
             pa.out = out;
         }
-        if (F->p.mfma)
-            hipLaunchKernelGGL((k_fno_layer<N, true, LAST>), dim3(grid(B)), dim3(FT), fused_lds<N>(W), F->stream,
-                               (const unsigned short*)ain, d.Wb, d.Wf, d.Kpad, d.Opad, bias, W, F->p.modes,
-                               (unsigned short*)aout, t1, tw, pa);
-        else
-            hipLaunchKernelGGL((k_fno_layer<N, false, LAST>), dim3(grid(B)), dim3(FT), fused_lds<N>(W), F->stream,
-                               (const float*)ain, d.Wb, d.Wf, d.Kpad, d.Opad, bias, W, F->p.modes, (float*)aout, t1, tw,
-                               pa);
+        // the layer's and the projection's K (both the width) in steps of 16
+        if (d.Kpad <= 32) layer_ks<LAST, 2>(F, d, bias, B, ain, aout, t1, tw, pa);
+        else layer_ks<LAST, 4>(F, d, bias, B, ain, aout, t1, tw, pa);
     }
 };
 

@@ -10,6 +10,8 @@
 #include "plan.h"
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4v __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 namespace pst {
@@ -71,6 +73,8 @@ struct pst_fno {
     float* modew;
     float *v, *s, *kb, *pre, *out, *dv, *ds, *dpre, *dout, *tmp;
     pst::cx<float> *specA, *specB, *ffttmp, *vst;
+    void* fact;               // fused inference activations: two slots of fact_slot bytes
+    int64_t fact_slot;
     float* part;
     double* lpart;
     float* coef;
@@ -80,9 +84,14 @@ struct pst_fno {
 
 namespace pst {
 
+// Channel stride of the fused inference activations ([b][point][channel]):
+// BF16 rows padded to whole 16-channel MFMA K steps, FP32 rows unpadded.
+__host__ __device__ constexpr int fno_act_cp(int W, bool bf) { return bf ? (W + 15) / 16 * 16 : W; }
+
 // Fused inference kernels (grid sizes n with an instantiation; false otherwise).
-// Activations between layers are BF16 when the operator runs on the matrix
-// cores, FP32 otherwise; t1 holds the x-transformed lines [b][c][z][y][kx < m].
+// Activations between layers ([b][point][channel], channel stride fno_act_cp)
+// are BF16 when the operator runs on the matrix cores, FP32 otherwise; t1 holds
+// the x-transformed lines [b][c][z][y][kx < m].
 bool fno_fused_supported(int n);
 //   v0 = lift(u) -> act, x r2c of v0 -> t1
 void fno_fused_lift(pst_fno* F, const float* u, int B, void* act, cx<float>* t1);
