@@ -326,8 +326,10 @@ def run_ensemble(pst, torch, I, steps=200, seq_steps=10):
     cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "pst_ensemble_autotune.json")
     variant = ens.autotune(cache)
     tuned = ens.get_mode()
+    q = ens.query()
     res = {"runs": len(sizes), "sizes": {"48": 32, "64": 48, "96": 16}, "variant": variant,
-           "tuned_mode": tuned, "grid_blocks": ens.query()["grid"]}
+           "class_variants": {str(n): v for n, v in zip(q["sizes"], ens.class_schedules())},
+           "tuned_mode": tuned, "grid_blocks": q["grid"]}
     timings = {}
     for mode, nst in (("graph", steps), ("batched_graph", steps), ("persistent", seq_steps),
                       ("batched", seq_steps), ("sequential", seq_steps)):

@@ -326,19 +326,28 @@ pst_status pst_ensemble_diagnostics(pst_ensemble *ens, double *energy, double *e
  * (b's pending work must be complete). */
 pst_status pst_ensemble_rel_l2(pst_ensemble *a, const pst_ensemble *b, double *per_run);
 
-/* Pick the schedule variant (radix order x tile lines) by timing each on
- * persistent steps (the state is saved and restored around the timing); then,
- * if the ensemble is in one of the two graph modes, switch it to whichever of
- * PERSISTENT_GRAPH and BATCHED_GRAPH steps faster (every mode gives bitwise
- * the same states).  cache_path (may be NULL) is a JSON object keyed by device
- * architecture, precision, RK order and the run sizes (the mode under the key
- * with "/mode" appended); cached choices are reused unless force != 0.
- * *chosen (may be NULL) receives the variant. */
+/* Pick the schedule variants (radix order x tile lines) by timing: the
+ * persistent kernel's one variant on persistent steps, then, size class by
+ * size class, the variant of that class's batched / sequential launches on
+ * batched steps (the state is saved and restored around the timing); then, if
+ * the ensemble is in one of the two graph modes, switch it to whichever of
+ * PERSISTENT_GRAPH and BATCHED_GRAPH steps faster (with one schedule, every
+ * mode gives bitwise the same states).  cache_path (may be NULL) is a JSON
+ * object keyed by device architecture, precision, RK order and the run sizes
+ * (the class variants under the key with "/class<c>" appended, the mode with
+ * "/mode"); cached choices are reused unless force != 0.  *chosen (may be
+ * NULL) receives the persistent kernel's variant. */
 pst_status pst_ensemble_autotune(pst_ensemble *ens, const char *cache_path, int force, int *chosen);
+/* One variant (0..3) for the persistent kernel and every class. */
 pst_status pst_ensemble_set_schedule(pst_ensemble *ens, int variant);
+/* The variant of one size class's batched and sequential launches (class
+ * index as in pst_ensemble_query; the persistent modes keep one variant). */
+pst_status pst_ensemble_set_class_schedule(pst_ensemble *ens, int cls, int variant);
+/* Per class (int[nclasses]): the variants of the batched launches. */
+pst_status pst_ensemble_class_schedules(const pst_ensemble *ens, int *variants);
 
-/* Distinct sizes (descending), runs per size, current variant and persistent
- * grid size.  Arrays need room for 4 entries; any pointer may be NULL. */
+/* Distinct sizes (descending), runs per size, the persistent kernel's variant
+ * and grid size.  Arrays need room for 4 entries; any pointer may be NULL. */
 pst_status pst_ensemble_query(const pst_ensemble *ens, int *nclasses, int *class_n, int *class_runs,
                               int *variant, int *grid);
 

@@ -227,7 +227,8 @@ struct pst_ensemble {
     std::vector<int> run_class, run_index;
     std::vector<EnsClassHost> cls;
     int mode;
-    int var;
+    int var;                      // schedule variant of the persistent kernel
+    int cvar[ENS_MAX_CLASSES];    // per class: the variant of its batched / sequential launches
     int grids[ENS_NVAR];
     EnsDesc<float> desc_host;     // last descriptor uploaded to desc_dev
     EnsDesc<float>* desc_dev;
@@ -257,12 +258,14 @@ static pst_status efail(pst_ensemble* E, pst_status s, const char* fmt, ...) {
     return s;
 }
 
-static EnsDesc<float> make_desc(pst_ensemble* E) {
+// per_class: the work units of each class follow its own variant (the
+// batched and sequential launches); else all follow the persistent kernel's.
+static EnsDesc<float> make_desc(pst_ensemble* E, bool per_class) {
     EnsDesc<float> d;
     memset(&d, 0, sizeof d);
     d.ncls = (int)E->cls.size();
-    const EnsKernels* K = ens_kernels(E->var);
     for (int i = 0; i < d.ncls; ++i) {
+        const EnsKernels* K = ens_kernels(per_class ? E->cvar[i] : E->var);
         const EnsClassHost& h = E->cls[i];
         EnsClass<float>& c = d.cls[i];
         c.geo = h.geo;
@@ -308,9 +311,10 @@ static int persistent_grid(const EnsKernels* K) {
 }
 
 static void launch_step(pst_ensemble* E) {
-    EnsDesc<float> d = make_desc(E);
-    const EnsKernels* K = ens_kernels(E->var);
-    if (E->mode == 0 || E->mode == 1) {
+    const bool pers = E->mode == 0 || E->mode == 1;
+    EnsDesc<float> d = make_desc(E, !pers);
+    if (pers) {
+        const EnsKernels* K = ens_kernels(E->var);
         // the descriptor only changes with the schedule: upload it when it does
         if (memcmp(&d, &E->desc_host, sizeof d) != 0) {
             E->desc_host = d;
@@ -323,6 +327,7 @@ static void launch_step(pst_ensemble* E) {
     for (int s = 0; s < d.nstages; ++s)
         for (int pass = 0; pass < 5; ++pass)
             for (int c = 0; c < d.ncls; ++c) {
+                const EnsKernels* K = ens_kernels(E->cvar[c]);
                 if (E->mode == 2 || E->mode == 4) K->launch_pass(d.cls[c], pass, s > 0, d.modes[s], d.h, E->stream);
                 else
                     for (int r = 0; r < d.cls[c].nruns; ++r)
@@ -466,6 +471,7 @@ extern "C" pst_status pst_ensemble_create(int nruns, const int* n, const pst_par
     hipLaunchKernelGGL(k_ens_reset_bar, dim3(1), dim3(64), 0, E->stream, E->bar);
     hipLaunchKernelGGL(k_ens_clear_err, dim3(1), dim3(64), 0, E->stream, E->err);
     E->var = 0;
+    for (int c = 0; c < ENS_MAX_CLASSES; ++c) E->cvar[c] = 0;
     for (int v = 0; v < ENS_NVAR; ++v) E->grids[v] = persistent_grid(ens_kernels(v));
     if (hipStreamSynchronize(E->stream) != hipSuccess) {
         g_ens_err = "initialisation failed";
@@ -588,7 +594,7 @@ extern "C" pst_status pst_ensemble_step(pst_ensemble* E, int nsteps) {
 extern "C" pst_status pst_ensemble_energy(pst_ensemble* E, double* per_run) {
     if (!E) return PST_ERR_INVALID_ARG;
     if (!per_run) return efail(E, PST_ERR_INVALID_ARG, "NULL output");
-    EnsDesc<float> d = make_desc(E);
+    EnsDesc<float> d = make_desc(E, false);
     for (int c = 0; c < d.ncls; ++c) {
         const EnsClassHost& h = E->cls[c];
         hipLaunchKernelGGL(k_ens_energy<float>, dim3((unsigned)h.runs.size()), dim3(256), 0, E->stream, d.cls[c],
@@ -606,11 +612,12 @@ extern "C" pst_status pst_ensemble_energy(pst_ensemble* E, double* per_run) {
 }
 
 // --------------------------------------------------------------- autotuner
-// For each class in turn, time every schedule (others fixed at their current
-// choice) on full persistent steps and keep the fastest.  Results are cached
-// in a flat JSON object {"<arch>/n<n>/<prec>": <variant>, ...} at cache_path
-// (NULL: no cache).  The ensemble state is saved and restored around the
-// timing runs.
+// The persistent kernel's variant is timed on full persistent steps; then, for
+// each class in turn (the others fixed at their current choice), the variant
+// of its batched launches on full batched steps; then the two graph modes.
+// Results are cached in a flat JSON object {"<key>": <variant>,
+// "<key>/class<c>": <variant>, "<key>/mode": <mode>} at cache_path (NULL: no
+// cache).  The ensemble state is saved and restored around the timing runs.
 static std::string arch_name() {
     int dev = 0;
     hipGetDevice(&dev);
@@ -662,17 +669,20 @@ extern "C" pst_status pst_ensemble_autotune(pst_ensemble* E, const char* cache_p
         key += (c ? "-" : "") + std::to_string(E->cls[c].n) + "x" + std::to_string(E->cls[c].runs.size());
     std::map<std::string, int> cache = read_cache(cache_path);
     const std::string mkey = key + "/mode";
+    auto ckey = [&](size_t c) { return key + "/class" + std::to_string(c); };
+    auto valid = [&](const std::string& k) { return cache.count(k) && cache[k] >= 0 && cache[k] < ENS_NVAR; };
     const bool graph_mode = E->mode == 0 || E->mode == 4;
-    if (!force && cache.count(key) && cache[key] >= 0 && cache[key] < ENS_NVAR) {
+    bool cached = !force && valid(key);
+    for (size_t c = 0; cached && c < E->cls.size(); ++c) cached = valid(ckey(c));
+    if (cached) {
         drop_graph(E);
         E->var = cache[key];
+        for (size_t c = 0; c < E->cls.size(); ++c) E->cvar[c] = cache[ckey(c)];
         if (graph_mode && cache.count(mkey) && (cache[mkey] == 0 || cache[mkey] == 4)) E->mode = cache[mkey];
         if (chosen) *chosen = E->var;
         return PST_OK;
     }
-    const int saved_mode = E->mode, saved_var = E->var;
-    E->mode = 1;  // time the persistent kernel directly
-    drop_graph(E);
+    const int saved_mode = E->mode;
     // save the state: the timing steps overwrite it
     std::vector<std::vector<char>> saved(E->cls.size());
     for (size_t c = 0; c < E->cls.size(); ++c) {
@@ -684,32 +694,54 @@ extern "C" pst_status pst_ensemble_autotune(pst_ensemble* E, const char* cache_p
     hipEvent_t a, b;
     hipEventCreate(&a);
     hipEventCreate(&b);
-    pst_status st = PST_OK;
-    float best = 1e30f;
-    int bestv = saved_var;
-    for (int v = 0; v < ENS_NVAR && st == PST_OK; ++v) {
-        E->var = v;
+    // milliseconds of 3 steps in the current mode, variant and class variants
+    auto time_steps = [&](float& ms) -> pst_status {
         launch_step(E);  // warm-up
         hipEventRecord(a, E->stream);
         for (int it = 0; it < 3; ++it) launch_step(E);
         hipEventRecord(b, E->stream);
-        if (hipEventSynchronize(b) != hipSuccess) {
-            st = efail(E, PST_ERR_HIP, "autotune timing failed");
-            break;
-        }
-        float ms = 0.f;
+        if (hipEventSynchronize(b) != hipSuccess) return efail(E, PST_ERR_HIP, "autotune timing failed");
         hipEventElapsedTime(&ms, a, b);
-        st = check_err_flag(E);
+        return E->mode <= 1 ? check_err_flag(E) : PST_OK;
+    };
+    pst_status st = PST_OK;
+    // 1. the persistent kernel's variant (one for all classes: one kernel)
+    E->mode = 1;
+    drop_graph(E);
+    float best = 1e30f;
+    int bestv = E->var;
+    for (int v = 0; v < ENS_NVAR && st == PST_OK; ++v) {
+        E->var = v;
+        float ms = 0.f;
+        st = time_steps(ms);
         if (st == PST_OK && ms < best) {
             best = ms;
             bestv = v;
         }
     }
-    // the graph modes with that variant: one persistent launch per step against
-    // the batched launches, each replayed from its graph
+    E->var = bestv;
+    // 2. each class's variant for the batched launches, the other classes
+    // fixed at their current choice (starting from the persistent pick)
+    E->mode = 2;
+    for (size_t c = 0; c < E->cls.size(); ++c) E->cvar[c] = bestv;
+    for (size_t c = 0; c < E->cls.size() && st == PST_OK; ++c) {
+        float cbest = 1e30f;
+        int cv = E->cvar[c];
+        for (int v = 0; v < ENS_NVAR && st == PST_OK; ++v) {
+            E->cvar[c] = v;
+            float ms = 0.f;
+            st = time_steps(ms);
+            if (st == PST_OK && ms < cbest) {
+                cbest = ms;
+                cv = v;
+            }
+        }
+        E->cvar[c] = cv;
+    }
+    // 3. the graph modes: one persistent launch per step against the batched
+    // launches, each replayed from its graph
     int mode_pick = saved_mode;
     if (st == PST_OK && graph_mode) {
-        E->var = bestv;
         float tbest = 1e30f;
         for (int m : {0, 4}) {
             E->mode = m;
@@ -738,9 +770,9 @@ extern "C" pst_status pst_ensemble_autotune(pst_ensemble* E, const char* cache_p
     for (size_t c = 0; c < E->cls.size(); ++c)
         hipMemcpy(E->cls[c].U, saved[c].data(), saved[c].size(), hipMemcpyHostToDevice);
     E->mode = mode_pick;
-    E->var = bestv;
     if (st != PST_OK) return st;
     cache[key] = bestv;
+    for (size_t c = 0; c < E->cls.size(); ++c) cache[ckey(c)] = E->cvar[c];
     if (graph_mode) cache[mkey] = mode_pick;
     write_cache(cache_path, cache);
     if (chosen) *chosen = bestv;
@@ -752,6 +784,22 @@ extern "C" pst_status pst_ensemble_set_schedule(pst_ensemble* E, int variant) {
     if (variant < 0 || variant >= ENS_NVAR) return efail(E, PST_ERR_INVALID_ARG, "variant %d", variant);
     drop_graph(E);
     E->var = variant;
+    for (int c = 0; c < ENS_MAX_CLASSES; ++c) E->cvar[c] = variant;
+    return PST_OK;
+}
+
+extern "C" pst_status pst_ensemble_set_class_schedule(pst_ensemble* E, int cls, int variant) {
+    if (!E) return PST_ERR_INVALID_ARG;
+    if (cls < 0 || cls >= (int)E->cls.size()) return efail(E, PST_ERR_INVALID_ARG, "class %d", cls);
+    if (variant < 0 || variant >= ENS_NVAR) return efail(E, PST_ERR_INVALID_ARG, "variant %d", variant);
+    drop_graph(E);
+    E->cvar[cls] = variant;
+    return PST_OK;
+}
+
+extern "C" pst_status pst_ensemble_class_schedules(const pst_ensemble* E, int* variants) {
+    if (!E || !variants) return PST_ERR_INVALID_ARG;
+    for (size_t c = 0; c < E->cls.size(); ++c) variants[c] = E->cvar[c];
     return PST_OK;
 }
 
@@ -770,7 +818,7 @@ extern "C" pst_status pst_ensemble_query(const pst_ensemble* E, int* nclasses, i
 
 extern "C" pst_status pst_ensemble_project(pst_ensemble* E) {
     if (!E) return PST_ERR_INVALID_ARG;
-    EnsDesc<float> d = make_desc(E);
+    EnsDesc<float> d = make_desc(E, false);
     for (int c = 0; c < d.ncls; ++c)
         hipLaunchKernelGGL(k_ens_project<float>, dim3(512), dim3(256), 0, E->stream, d.cls[c]);
     hipError_t e = hipGetLastError();
@@ -780,7 +828,7 @@ extern "C" pst_status pst_ensemble_project(pst_ensemble* E) {
 extern "C" pst_status pst_ensemble_diagnostics(pst_ensemble* E, double* energy, double* enstrophy) {
     if (!E) return PST_ERR_INVALID_ARG;
     if (!energy || !enstrophy) return efail(E, PST_ERR_INVALID_ARG, "NULL output");
-    EnsDesc<float> d = make_desc(E);
+    EnsDesc<float> d = make_desc(E, false);
     for (int c = 0; c < d.ncls; ++c) {
         const EnsClassHost& h = E->cls[c];
         const size_t R = h.runs.size();
@@ -808,7 +856,7 @@ extern "C" pst_status pst_ensemble_rel_l2(pst_ensemble* A, const pst_ensemble* B
     for (size_t c = 0; c < A->cls.size(); ++c)
         if (A->cls[c].n != Bn->cls[c].n || A->cls[c].runs != Bn->cls[c].runs)
             return efail(A, PST_ERR_INVALID_ARG, "ensembles differ");
-    EnsDesc<float> da = make_desc(A), db = make_desc(const_cast<pst_ensemble*>(Bn));
+    EnsDesc<float> da = make_desc(A, false), db = make_desc(const_cast<pst_ensemble*>(Bn), false);
     for (int c = 0; c < da.ncls; ++c) {
         const EnsClassHost& h = A->cls[c];
         const size_t R = h.runs.size();

@@ -47,8 +47,8 @@ template <> struct Act<false> {
 // row stride PXS = RB n + 1 puts the channels of one point on distinct banks
 // (the activation store phase reads 8 channels of a point per lane).
 template <int N> constexpr int xstride() { return fno_rows<N>() * N + 1; }
-// floats of X, rounded up so that the FFT line scratch after it is 8-byte aligned
-template <int N> __host__ __device__ constexpr int xfloats(int W) { return (W * xstride<N>() + 1) / 2 * 2; }
+// floats of X, rounded up so that the FFT line scratch after it is 16-byte aligned
+template <int N> __host__ __device__ constexpr int xfloats(int W) { return (W * xstride<N>() + 3) / 4 * 4; }
 // bytes of dynamic LDS: X, then one FFT line scratch per pair slot
 template <int N> size_t fused_lds(int W) {
     return sizeof(float) * (size_t)xfloats<N>(W) + sizeof(cx<float>) * (size_t)(FT / NCfg<N>::G) * LineLds<float>::size(N);
@@ -357,13 +357,31 @@ __global__ __launch_bounds__(FT) void k_fno_layer(const typename Act<BF>::T* __r
             if constexpr (BF) acc = mfma_tile<KS>(pops, pa.Wb, pa.Kpad, pa.Kpad / 16, ht, n, kg);
             else acc = fma_tile(pa.Wf, pa.Kpad, W, ht, X + pt0 + n, (int64_t)PXS, kg);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int h = ht * 32 + 8 * (r / 4) + 4 * kg + (r % 4);
-                if (h >= pa.H) continue;
-                const float a = gelu_f(acc[r] + wl[h]);
-                y0 += wl[pa.H + h] * a;
-                y1 += wl[2 * pa.H + h] * a;
-                y2 += wl[3 * pa.H + h] * a;
+            for (int i = 0; i < 4; ++i) {
+                // hidden units h0 .. h0 + 3 (consecutive): their bias and output
+                // weights as one 16-byte LDS read each where aligned
+                const int h0 = ht * 32 + 8 * i + 4 * kg;
+                if (h0 + 4 <= pa.H && pa.H % 4 == 0) {
+                    const float4 bq = *(const float4*)(wl + h0);
+                    const float4 w0 = *(const float4*)(wl + pa.H + h0);
+                    const float4 w1 = *(const float4*)(wl + 2 * pa.H + h0);
+                    const float4 w2 = *(const float4*)(wl + 3 * pa.H + h0);
+                    const float a0 = gelu_f(acc[4 * i] + bq.x), a1 = gelu_f(acc[4 * i + 1] + bq.y);
+                    const float a2 = gelu_f(acc[4 * i + 2] + bq.z), a3 = gelu_f(acc[4 * i + 3] + bq.w);
+                    y0 += w0.x * a0 + w0.y * a1 + w0.z * a2 + w0.w * a3;
+                    y1 += w1.x * a0 + w1.y * a1 + w1.z * a2 + w1.w * a3;
+                    y2 += w2.x * a0 + w2.y * a1 + w2.z * a2 + w2.w * a3;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int h = h0 + j;
+                        if (h >= pa.H) continue;
+                        const float a = gelu_f(acc[4 * i + j] + wl[h]);
+                        y0 += wl[pa.H + h] * a;
+                        y1 += wl[2 * pa.H + h] * a;
+                        y2 += wl[3 * pa.H + h] * a;
+                    }
+                }
             }
         }
         // the two half-waves hold disjoint hidden units of the same points

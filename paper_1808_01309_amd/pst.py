@@ -92,6 +92,7 @@ _ens_sigs = [("pst_ensemble_create", [_I, _P, ctypes.POINTER(pst_params), _P, ct
              ("pst_ensemble_get_mode", [_P, _P]),
              ("pst_ensemble_energy", [_P, _P]), ("pst_ensemble_autotune", [_P, ctypes.c_char_p, _I, _P]),
              ("pst_ensemble_set_schedule", [_P, _I]), ("pst_ensemble_query", [_P, _P, _P, _P, _P, _P]),
+             ("pst_ensemble_set_class_schedule", [_P, _I, _I]), ("pst_ensemble_class_schedules", [_P, _P]),
              ("pst_ensemble_project", [_P]), ("pst_ensemble_diagnostics", [_P, _P, _P]),
              ("pst_ensemble_rel_l2", [_P, _P, _P]),
              ("pst_ensemble_set_spin_limit", [_P, ctypes.c_longlong])]
@@ -129,6 +130,7 @@ EXPORTED = ["pst_fno_create", "pst_fno_destroy", "pst_fno_last_error", "pst_fno_
             "pst_ensemble_get_state", "pst_ensemble_step", "pst_ensemble_set_mode", "pst_ensemble_get_mode",
             "pst_ensemble_energy",
             "pst_ensemble_autotune", "pst_ensemble_set_schedule", "pst_ensemble_query", "pst_ensemble_project",
+            "pst_ensemble_set_class_schedule", "pst_ensemble_class_schedules",
             "pst_ensemble_diagnostics", "pst_ensemble_rel_l2", "pst_ensemble_set_spin_limit",
             "pst_status_str", "pst_last_error", "pst_supported_n", "pst_plan_create", "pst_plan_destroy",
             "pst_set_state", "pst_get_state", "pst_set_forcing", "pst_rhs", "pst_step", "pst_energy", "pst_enstrophy",
@@ -491,6 +493,16 @@ class Ensemble:
 
     def set_schedule(self, variant):
         self._check(lib.pst_ensemble_set_schedule(self._h, variant))
+
+    def set_class_schedule(self, cls, variant):
+        """Variant of one size class's batched / sequential launches."""
+        self._check(lib.pst_ensemble_set_class_schedule(self._h, int(cls), int(variant)))
+
+    def class_schedules(self):
+        nc = self.query()["sizes"]
+        out = (ctypes.c_int * max(len(nc), 1))()
+        self._check(lib.pst_ensemble_class_schedules(self._h, out))
+        return list(out[:len(nc)])
 
     def set_spin_limit(self, polls):
         """Test only: polls of a device-wide barrier before it reports a timeout."""

@@ -77,6 +77,29 @@ def test_variants_match_oracle(P, init, ref, variant):
         assert rel(out[r], ref[r]) < 1e-5
 
 
+def test_class_schedules(P, init, ref):
+    """Each size class's batched launches run their own variant: a mixed
+    schedule gives, run by run, bitwise the states of the uniform schedule of
+    that run's class (the classes are independent), and they match the oracle."""
+    mixed = [1, 3, 0, 2]            # classes 96, 64, 48, 32 (query order)
+    ens = P.Ensemble(SIZES, rk_order=RK, nu=NU, dt=DT)
+    ens.set_mode("batched_graph")
+    for c, v in enumerate(mixed):
+        ens.set_class_schedule(c, v)
+    assert ens.class_schedules() == mixed
+    for r, u in enumerate(init):
+        ens.set_state(r, u)
+    ens.step(NSTEPS)
+    out = [ens.get_state(r) for r in range(len(SIZES))]
+    order = ens.query()["sizes"]
+    ens.close()
+    uniform = {v: run_mode(P, init, "batched", v)[0] for v in set(mixed)}
+    for r, n in enumerate(SIZES):
+        v = mixed[order.index(n)]
+        assert np.array_equal(out[r], uniform[v][r]), (r, n, v)
+        assert rel(out[r], ref[r]) < 1e-5
+
+
 def test_graph_replay_many_steps(O, P):
     """Replaying a captured step 20 times (persistent or batched graph, with
     host work and a synchronisation between replays) equals 20 directly
@@ -113,14 +136,21 @@ def test_autotune_and_cache(P, init, tmp_path):
         assert np.array_equal(ens.get_state(r), before[r])
     cache = json.load(open(path))
     keys = sorted(cache)
-    assert len(keys) == 2 and keys[1] == keys[0] + "/mode"
-    assert cache[keys[0]] == v
+    base = keys[0]
+    ncls = len(ens.query()["sizes"])
+    assert sorted(keys) == sorted([base, base + "/mode"] + [f"{base}/class{c}" for c in range(ncls)])
+    assert cache[base] == v
+    # per size class: the variant of its batched launches
+    cv = ens.class_schedules()
+    assert len(cv) == ncls and all(0 <= x < 4 for x in cv)
+    assert [cache[f"{base}/class{c}"] for c in range(ncls)] == cv
     # the default (graph) ensemble is switched to the faster graph mode
     mode = ens.get_mode()
-    assert mode in ("graph", "batched_graph") and cache[keys[1]] == {"graph": 0, "batched_graph": 4}[mode]
+    assert mode in ("graph", "batched_graph") and cache[base + "/mode"] == {"graph": 0, "batched_graph": 4}[mode]
     assert ens.query()["variant"] == v
     ens2 = P.Ensemble(SIZES, rk_order=RK, nu=NU, dt=DT)
     assert ens2.autotune(path) == v        # served from the cache
+    assert ens2.class_schedules() == cv
     assert ens2.get_mode() == mode
     assert ens2.query()["sizes"] == [96, 64, 48, 32]
     assert ens2.query()["runs"] == [1, 1, 2, 2]
@@ -134,6 +164,10 @@ def test_ensemble_errors(P):
         ens.set_state(3, np.zeros((3, 32, 32, 17), np.complex64))
     with pytest.raises(P.PstError):
         ens.set_mode(9)
+    with pytest.raises(P.PstError):
+        ens.set_class_schedule(1, 0)     # one class only
+    with pytest.raises(P.PstError):
+        ens.set_class_schedule(0, 4)
 
 
 def test_project_diagnostics_distance(O, P):
