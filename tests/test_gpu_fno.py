@@ -1,8 +1,7 @@
 """GPU FNO against the FP64 FNO oracle: forward output and every parameter
-gradient, for the FP32 kernels (relative L2 <= 1e-5 forward, <= 1e-4 per
-gradient group) and the BF16 matrix-core kernels (<= 2e-2 forward,
-<= 5e-2 per gradient group: BF16 operands carry ~4e-3 relative rounding).
-Inputs are the float32-rounded copies the GPU receives."""
+gradient, for the FP32 kernels (relative L2 <= 1e-5, forward and per gradient
+group) and the BF16 matrix-core kernels (<= 2e-2: BF16 operands carry ~4e-3
+relative rounding).  Inputs are the float32-rounded copies the GPU receives."""
 import numpy as np
 import pytest
 
@@ -53,7 +52,9 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("mfma,tf,tg", [(False, 1e-5, 1e-4), (True, 2e-2, 5e-2)])
+# FP32 <= 1e-5 and BF16 <= 2e-2 for the forward pass and every gradient group
+# (measured: FP32 <= 5e-7, BF16 forward 4.6e-3, gradients <= 9e-3)
+@pytest.mark.parametrize("mfma,tf,tg", [(False, 1e-5, 1e-5), (True, 2e-2, 2e-2)])
 def test_forward_and_gradients(P, torch, case, mfma, tf, tg, errlog):
     theta, u, tgt, out_ref, L_ref, g_ref = case
     fno = P.FNO(batch=B, mfma=mfma, **CFG)
