@@ -6,9 +6,8 @@
 //   K_l(v) = c2r(R_l . r2c(v) on the retained modes).
 //
 // Channel mixing (every dense layer, forward and backward) is a GEMM over
-// points on the matrix cores: v_mfma_f32_32x32x16_bf16 (forward) and
-// v_mfma_f32_32x32x8_bf16 (weight gradients) with BF16 weights and
-// activations and FP32 accumulation (an FP32 FMA variant of the same kernels
+// points on the matrix cores: gfx950's v_mfma_f32_32x32x16_bf16 with BF16
+// weights and activations and FP32 accumulation (an FP32 FMA variant of the same kernels
 // exists for gradient checks).  The spectral layers run the library's own 3D
 // r2c / c2r transform kernels; the per-mode complex channel mixing and its
 // adjoint are FP32.  Activations are stored FP32, channel-major
@@ -101,7 +100,7 @@ __global__ __launch_bounds__(GT) void k_gemm(const unsigned short* __restrict__ 
 }
 
 // Partial weight gradients: dW[o][k] = sum_{b,p} Y[b][o][p] X'[b][k][p] over
-// this block's points (8 per MFMA step), tile (ot, kt) = blockIdx.y.
+// this block's points (16 per MFMA step), tile (ot, kt) = blockIdx.y.
 template <bool MFMA, bool GELU_X>
 __global__ __launch_bounds__(GT) void k_wgrad(const float* __restrict__ Y, int O, const float* __restrict__ X, int K,
                                               int P, int64_t total, int64_t ppb, int ktiles,
@@ -114,19 +113,27 @@ __global__ __launch_bounds__(GT) void k_wgrad(const float* __restrict__ Y, int O
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    // points per step: 16 (one 32x32x16 MFMA) or 8; P and the block ranges are multiples of 16
+    constexpr int PS = MFMA ? 16 : 8;
     const int64_t beg = (int64_t)blockIdx.x * ppb, end = beg + ppb < total ? beg + ppb : total;
-    for (int64_t q = beg + (int64_t)wave * 8; q < end; q += 8 * (GT / 64)) {
+    for (int64_t q = beg + (int64_t)wave * PS; q < end; q += PS * (GT / 64)) {
         const int b = (int)(q / P), p = (int)(q % P);
         if constexpr (MFMA) {
-            bf16x4 aa, bb;
-            const float4 ya = om < O ? *(const float4*)(Y + ((int64_t)b * O + om) * P + p + 4 * kg) : make_float4(0, 0, 0, 0);
-            float4 xb = kn < K ? *(const float4*)(X + ((int64_t)b * K + kn) * P + p + 4 * kg) : make_float4(0, 0, 0, 0);
-            if (GELU_X && kn < K) {
-                xb.x = gelu_f(xb.x); xb.y = gelu_f(xb.y); xb.z = gelu_f(xb.z); xb.w = gelu_f(xb.w);
+            // lane n + 32 kg: points p + 8 kg .. + 7 of row om (A) and column kn (B)
+            bf16x8v aa, bb;
+            const float* yr = Y + ((int64_t)b * O + om) * P + p + 8 * kg;
+            const float* xr = X + ((int64_t)b * K + kn) * P + p + 8 * kg;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float4 ya = om < O ? *(const float4*)(yr + 4 * h) : make_float4(0, 0, 0, 0);
+                float4 xb = kn < K ? *(const float4*)(xr + 4 * h) : make_float4(0, 0, 0, 0);
+                if (GELU_X && kn < K) {
+                    xb.x = gelu_f(xb.x); xb.y = gelu_f(xb.y); xb.z = gelu_f(xb.z); xb.w = gelu_f(xb.w);
+                }
+                aa[4 * h] = (__bf16)ya.x; aa[4 * h + 1] = (__bf16)ya.y; aa[4 * h + 2] = (__bf16)ya.z; aa[4 * h + 3] = (__bf16)ya.w;
+                bb[4 * h] = (__bf16)xb.x; bb[4 * h + 1] = (__bf16)xb.y; bb[4 * h + 2] = (__bf16)xb.z; bb[4 * h + 3] = (__bf16)xb.w;
             }
-            aa[0] = (short)f2bf(ya.x); aa[1] = (short)f2bf(ya.y); aa[2] = (short)f2bf(ya.z); aa[3] = (short)f2bf(ya.w);
-            bb[0] = (short)f2bf(xb.x); bb[1] = (short)f2bf(xb.y); bb[2] = (short)f2bf(xb.z); bb[3] = (short)f2bf(xb.w);
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(aa, bb, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa, bb, acc, 0, 0, 0);
         } else {
             for (int j = 0; j < 8; ++j) {
                 float x = kn < K ? X[((int64_t)b * K + kn) * P + p + j] : 0.f;

@@ -92,13 +92,16 @@ def test_adam_reduces_loss(P, torch, case, mfma):
 
 # Shapes that exercise the inference kernels' edge cases: an odd radix (24),
 # odd channel counts (an unpaired last line), more than 32 channels or hidden
-# units (several matrix tiles, masked rows), one row per block (96, 128) and a
-# single layer (lift straight into the projection).
+# units (several matrix tiles, masked rows), one row per block (96, 128), a
+# single layer (lift straight into the projection), and n = 64: the
+# benchmark's width and modes, and 20 channels with 16 modes.
 SHAPES = [
     dict(n=24, width=5, modes=4, layers=2, hidden=40),
     dict(n=48, width=36, modes=5, layers=1, hidden=16),
     dict(n=96, width=3, modes=6, layers=2, hidden=8),
     dict(n=128, width=2, modes=4, layers=1, hidden=8),
+    dict(n=64, width=32, modes=12, layers=2, hidden=16),
+    dict(n=64, width=20, modes=16, layers=1, hidden=8),
 ]
 
 
