@@ -1071,7 +1071,8 @@ extern "C" pst_status pst_project(pst_plan* P, void* spec_dev, int ngroups, doub
     const bool diag = energy || enstrophy;
     double* part = nullptr;
     if (diag) {
-        // partials and results after any other scratch of the plan's spectral buffer
+        // partials and results in the plan's spectral scratch (stream-ordered
+        // after any earlier call that used it; grown with a synchronisation)
         const size_t need = sizeof(double) * (size_t)ngroups * (2 * PROJ_BLOCKS + 2);
         pst_status s = ensure_abi(P, need);
         if (s) return s;
