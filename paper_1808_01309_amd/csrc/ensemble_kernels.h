@@ -109,7 +109,8 @@ __device__ __forceinline__ void ens_unit_v(const EnsClass<T>& c, int pass, int s
             zinv_body<T, LC, ENS_NT, 1>(st, A, c.tw, g, lu, tid, sm);
         } break;
         case 1: ypass_body<T, TC, ENS_NT, true, TC::N>(A, B, c.tw, g, g.sa, g.sb, 6, lu, tid, sm); break;
-        case 2: xpass_body<T, TC, ENS_NT, 0>(B, C, c.tw, g, lu, tid, sm); break;
+        // ensemble grids use the 2/3 rule: the cutoff is compiled in
+        case 2: xpass_body<T, TC, ENS_NT, 0, false, false, (N + 2) / 3 - 1>(B, C, c.tw, g, lu, tid, sm); break;
         case 3: ypass_body<T, TC, ENS_NT, false, TC::N>(C, A, c.tw, g, g.sb, g.sa, 3, lu, tid, sm); break;
         default: {
             RkArgs<T> ra;

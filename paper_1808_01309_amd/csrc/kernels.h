@@ -273,9 +273,10 @@ __device__ __forceinline__ void ypass_body(const cx<T>* __restrict__ in, cx<T>* 
     const int kx = (int)(rest % geo.nxk), f = (int)(rest / geo.nxk);
     const int z = zt * TL + t;
     const bool zin = valid && z < nz;
-    const int rows_in = INV ? geo.My : N, rows_out = INV ? N : geo.My;
-    const cx<T>* src = in + f * fs_in + (int64_t)kx * rows_in * nz + z;
-    cx<T>* dst = out + f * fs_out + (int64_t)kx * rows_out * nz + z;
+    // kx plane strides: My nz on the A side, pb (padded) on the B / C side
+    const int64_t pa = (int64_t)geo.My * nz;
+    const cx<T>* src = in + f * fs_in + (int64_t)kx * (INV ? pa : geo.pb) + z;
+    cx<T>* dst = out + f * fs_out + (int64_t)kx * (INV ? geo.pb : pa) + z;
     cx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -310,7 +311,10 @@ __global__ __launch_bounds__((CF::G * CF::TL)) void k_ypass(const cx<T>* __restr
 // price of one), cross products in registers, forward x of the products
 // packed two per complex line, split by Hermitian symmetry, kx <= K kept.
 // SYS: 0 Navier-Stokes, 1 MHD, 2 Boussinesq (nbv: Brunt-Vaisala frequency).
-template <typename T, class CF, int NT, int SYS, bool PPB = false, bool BLK = false>
+// KC: the x cutoff Kx as a compile-time constant (0: read from geo), which
+// lets the compiler drop the loads, selects and stores of the rows and points
+// that lie wholly inside or outside the kept band.
+template <typename T, class CF, int NT, int SYS, bool PPB = false, bool BLK = false, int KC = 0>
 __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
                                            const cx<T>* __restrict__ tw, const Geo& geo, int64_t unit, int tid,
                                            cx<T>* sm, T nbv = T(0)) {
@@ -346,9 +350,9 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     const TV lds{sm + s * TSZ1 + t};
     const TV lds1{sm + (PPB ? TSZ : 0) + s * TSZ1 + t};
     int ex = 0;   // LDS phases so far
-    const int64_t nn = (int64_t)geo.ny * nz;   // stride of one kx plane
+    const int64_t nn = geo.pb;   // stride of one kx plane
     const int64_t off = (int64_t)y * nz + z;
-    const int K = geo.Kx;
+    const int K = KC ? KC : geo.Kx;
     // Each kept row kx <= K of a pair (v, i k x v) is read from HBM once into
     // LDS (coalesced along z); the packed line Z = V + i W and its Hermitian
     // mirror Z(N - kx) = conj V + i conj W are then assembled from LDS.
@@ -555,7 +559,7 @@ template <typename T, class CF, int SYS> constexpr int xpass_per() {
     else return ((sizeof(T) == 8 || CF::TL < tile_lines<T>()) && xpass_pp<T, CF, SYS == 1>()) ? 32 : 1;
 }
 
-template <typename T, class CF, int SYS>
+template <typename T, class CF, int SYS, int KC = 0>
 __global__ __launch_bounds__((CF::G * CF::TL), (xpass_two_per_cu<T, CF::N, SYS>() ? 4 : 1)) void k_xpass(const cx<T>* __restrict__ Bf, cx<T>* __restrict__ Cf,
                                                           const cx<T>* __restrict__ tw, Geo geo, T nbv) {
     constexpr bool PPB = xpass_pp<T, CF, SYS == 1>();
@@ -564,14 +568,14 @@ __global__ __launch_bounds__((CF::G * CF::TL), (xpass_two_per_cu<T, CF::N, SYS>(
     // each XCD takes a contiguous range of tiles (measured faster, most for the
     // narrow MHD tiles at n = 1024 whose rows share cache lines)
     if constexpr (PER == 1) {
-        xpass_body<T, CF, CF::G * CF::TL, SYS, PPB, true>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm, nbv);
+        xpass_body<T, CF, CF::G * CF::TL, SYS, PPB, true, KC>(Bf, Cf, tw, geo, xcd_unit(), threadIdx.x, sm, nbv);
     } else {
         const int64_t ntl = (int64_t)geo.ny * zt_count<CF::TL>(geo);
         const int64_t u0 = xcd_unit() * PER;
         const int64_t u1 = u0 + PER < ntl ? u0 + PER : ntl;
         for (int64_t u = u0; u < u1; ++u) {
             if (u > u0) __syncthreads();   // the previous tile's last LDS reads
-            xpass_body<T, CF, CF::G * CF::TL, SYS, PPB, true>(Bf, Cf, tw, geo, u, threadIdx.x, sm, nbv);
+            xpass_body<T, CF, CF::G * CF::TL, SYS, PPB, true, KC>(Bf, Cf, tw, geo, u, threadIdx.x, sm, nbv);
         }
     }
 }
@@ -1066,7 +1070,7 @@ __device__ __forceinline__ void xpass_gpe_body(const cx<T>* __restrict__ Bf, cx<
     // two LDS buffers used by alternate exchanges: one barrier per exchange
     constexpr int TSZ1 = TileBlk<T, TL>::size(N), TSZ = SG * TSZ1;
     const TileBlk<T, TL> lds0{sm + s * TSZ1 + t}, lds1{sm + TSZ + s * TSZ1 + t};
-    const int64_t nn = (int64_t)geo.ny * nz, off = (int64_t)y * nz + z;
+    const int64_t nn = geo.pb, off = (int64_t)y * nz + z;
     cx<T> v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -1278,23 +1282,33 @@ struct Impl {
                                (const cx<T>*)P->B, (cx<T>*)P->C, (const cx<T>*)twid(P), g);
         } else if (P->p.solver == PST_MHD) {
             using XC = XCfg<T, N, true>;
-            hipLaunchKernelGGL((k_xpass<T, XC, 1>), dim3((unsigned)xtile_units<XC, XC::G * XC::TL>(g)),
-                               dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
-                               (const cx<T>*)twid(P), g, T(0));
+            xpass_launch<XC, 1>(P, dim3((unsigned)xtile_units<XC, XC::G * XC::TL>(g)), T(0));
         } else if (P->p.solver == PST_BOUSSINESQ) {
             // five backward pairs: the MHD tile (half the lines) keeps them in registers
             using XC = XCfg<T, N, true>;
             constexpr int per = xpass_per<T, XC, 2>();
-            hipLaunchKernelGGL((k_xpass<T, XC, 2>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(g), per)),
-                               dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
-                               (const cx<T>*)twid(P), g, (T)P->p.nbv);
+            xpass_launch<XC, 2>(P, dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(g), per)), (T)P->p.nbv);
         } else {
             using XC = XCfg<T, N, false>;
             constexpr int per = xpass_per<T, XC, 0>();
-            hipLaunchKernelGGL((k_xpass<T, XC, 0>), dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(g), per)),
-                               dim3(XC::G * XC::TL), 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
-                               (const cx<T>*)twid(P), g, T(0));
+            xpass_launch<XC, 0>(P, dim3(cdiv(xtile_units<XC, XC::G * XC::TL>(g), per)), T(0));
         }
+    }
+    // The 2/3-rule cutoff of an n-point x axis (the largest K with 3K < n) is
+    // compiled into the kernel; other cutoffs take the runtime form, and so
+    // does the FP64 Navier-Stokes pass at n = 1024 (its fixed-cutoff form
+    // spills registers).
+    template <class XC, int SYS>
+    static void xpass_launch(pst_plan* P, dim3 grid, T nbv) {
+        constexpr int K23 = (N + 2) / 3 - 1;
+        constexpr bool FIX = !(sizeof(T) == 8 && N >= 1024 && SYS == 0);
+        const dim3 block(XC::G * XC::TL);
+        if (FIX && P->geo.Kx == K23)
+            hipLaunchKernelGGL((k_xpass<T, XC, SYS, FIX ? K23 : 0>), grid, block, 0, P->stream, (const cx<T>*)P->B,
+                               (cx<T>*)P->C, (const cx<T>*)twid(P), P->geo, nbv);
+        else
+            hipLaunchKernelGGL((k_xpass<T, XC, SYS>), grid, block, 0, P->stream, (const cx<T>*)P->B, (cx<T>*)P->C,
+                               (const cx<T>*)twid(P), P->geo, nbv);
     }
     static void yfwd(pst_plan* P) {
         KTimer tm(P, PST_K_YFWD);
