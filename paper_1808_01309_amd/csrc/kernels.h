@@ -362,8 +362,13 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
     // are in flight together), and the next pair's loads are issued before the
     // current pair's LDS barrier and assembly, which hides their latency.
     constexpr int IT = (N / 2 - 1) / G + 1;
-    cx<T> la[IT], lb[IT];
+    // FP32 Navier-Stokes: all three pairs are loaded at the start of the tile
+    constexpr bool ALLP = sizeof(T) == 4 && SYS == 0;
+    constexpr int NSL = ALLP ? NP : 1;   // pair slots in registers
+    cx<T> la_[NSL][IT], lb_[NSL][IT];
     auto load_pair = [&](int pi, bool zin_, int64_t off_) {
+        cx<T>(&la)[IT] = la_[ALLP ? pi : 0];
+        cx<T>(&lb)[IT] = lb_[ALLP ? pi : 0];
         // pairs (v_c, (i k x v)_c); Boussinesq adds (theta_x, theta_y), (theta_z, theta)
         const int fu = (BQ && pi >= 3) ? 6 + 2 * (pi - 3) : (pi / 3) * 6 + pi % 3;
         const int fw = (BQ && pi >= 3) ? fu + 1 : fu + 3;
@@ -375,9 +380,16 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
             lb[i] = ok ? Bf[fw * geo.sb + kx * nn + off_] : czero<T>();
         }
     };
-    load_pair(0, zin, off);
+    if constexpr (ALLP) {
+#pragma unroll
+        for (int pi = 0; pi < NP; ++pi) load_pair(pi, zin, off);
+    } else {
+        load_pair(0, zin, off);
+    }
 #pragma unroll
     for (int pi = 0; pi < NP; ++pi) {
+        cx<T>(&la)[IT] = la_[ALLP ? pi : 0];
+        cx<T>(&lb)[IT] = lb_[ALLP ? pi : 0];
         // this tile's LDS, points 0 .. 2K+1 < N of the tile view
         const TV stage{sm + ((PPB && (ex & 1)) ? TSZ : 0) + s * TSZ1 + t};
 #pragma unroll
@@ -393,7 +405,7 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
                 }
             }
         }
-        if (pi + 1 < NP) load_pair(pi + 1, zin, off);
+        if (!ALLP && pi + 1 < NP) load_pair(pi + 1, zin, off);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -491,6 +503,10 @@ __device__ __forceinline__ void xpass_body(const cx<T>* __restrict__ Bf, cx<T>* 
         const TV lo = (PPB && (ex & 1)) ? lds1 : lds;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
+            // with a compiled-in cutoff, points that no thread's kept row
+            // kx <= K or mirror N - kx needs are neither stored nor computed
+            const int d = FF::last_pos(0, e);
+            if (KC && FF::R_LAST * G == N && d > K && d + G - 1 < N - K) continue;
             if constexpr (SPLIT) lo.at(g, FF::last_pos(0, e)) = v[po][e];
             else lo(FF::last_pos(g, e)) = v[po][e];
         }
