@@ -45,10 +45,11 @@ constexpr int xpass_lines() {
     // FP32 Navier-Stokes: 8 lines below n = 1024, 4 at 1024 (128 threads per
     // line there), two workgroups per CU
     if (sizeof(T) == 4 && !MHD) return N < 1024 ? 8 : 4;
-    // FP32 MHD at n = 1024: 2 lines of 128 threads (176 VGPRs: two 256-thread
-    // workgroups per CU rather than one of 512; 43.0 -> 41.4 ms at 1024^3;
-    // the same halving of the 512^3 Boussinesq tile measured 2.95 -> 4.62 ms)
-    if (sizeof(T) == 4 && N >= 1024) return 2;
+    // FP32 MHD at n = 1024: 4 lines of 128 threads (172 VGPRs, one 512-thread
+    // workgroup per CU), whose 32-byte rows of the padded kx planes read
+    // faster than the 16-byte rows of 2-line tiles (x pass 41.1 -> 32.8 ms at
+    // 1024^3; halving the 512^3 Boussinesq tile measured 2.95 -> 4.62 ms)
+    if (sizeof(T) == 4 && N >= 1024) return 4;
     return tile_lines<T>() / (MHD ? 2 : 1) / (N >= 1024 ? 2 : 1);
 }
 constexpr int LINE_BLOCK = 256;

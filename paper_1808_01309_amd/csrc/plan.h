@@ -22,12 +22,11 @@ namespace pst {
 //   state   [ncomp][nxk][My][M]   (kx, jy, jz)       component stride sc
 //   A, D    [nf][nxk][My][n]      (kx, jy, z)        field stride sa
 //   B, C    [nf][nxk][ny][n]      (kx, y, z)         field stride sb, kx plane
-//           stride pb = ny n + pad (BC_PAD elements; the plan may choose 0):
-//           the unpadded plane stride is a power of two for the power-of-two
-//           grids (2 MB at 512^3 FP32), and the x pass, which reads one short z
-//           row from each kx plane, then spreads its reads over few memory
-//           channels (a memory-only kernel with the x pass's 512^3 access
-//           pattern: 1.03 ms unpadded, 0.72 ms padded)
+//           stride pb = ny n + BC_PAD: the unpadded plane stride is a power
+//           of two for the power-of-two grids (2 MB at 512^3 FP32), and the x
+//           pass, which reads one short z row from each kx plane, then spreads
+//           its reads over few memory channels (a memory-only kernel with the
+//           x pass's 512^3 access pattern: 1.03 ms unpadded, 0.72 ms padded)
 //   full = 1 (Gross-Pitaevskii): kx runs over the whole axis like ky and kz
 //   (compact index jx in [0, 2Kx + 1), nxk = 2Kx + 1); full = 0: kx = jx in [0, Kx].
 // Physical wavenumber of index k on axis i: a_i k, a_i = 2 pi / L_i (1 for
@@ -45,8 +44,7 @@ struct Geo {
 
 // Geometry of an nx x ny x nz grid with cutoffs Kx, Ky, Kz, wavenumber scales
 // a_i = 2 pi / L_i; full: kx over the whole axis (complex fields).
-inline Geo make_geo(int nx, int ny, int nz, int Kx, int Ky, int Kz, double ax, double ay, double az, int full,
-                    int bc_pad = BC_PAD) {
+inline Geo make_geo(int nx, int ny, int nz, int Kx, int Ky, int Kz, double ax, double ay, double az, int full) {
     Geo g{};
     g.n = nz;
     g.K = Kz;
@@ -60,7 +58,7 @@ inline Geo make_geo(int nx, int ny, int nz, int Kx, int Ky, int Kz, double ax, d
     g.nxk = full ? 2 * Kx + 1 : Kx + 1;
     g.sc = (int64_t)g.nxk * g.My * g.M;
     g.sa = (int64_t)g.nxk * g.My * nz;
-    g.pb = (int64_t)ny * nz + bc_pad;
+    g.pb = (int64_t)ny * nz + BC_PAD;
     g.sb = (int64_t)g.nxk * g.pb;
     g.ax = ax;
     g.ay = ay;

@@ -579,11 +579,8 @@ extern "C" pst_status pst_plan_create(const pst_params* p, void* hip_stream, pst
         return gpe ? (m + 3) / 4 - 1 : p->dealias == PST_DEALIAS_NONE ? m / 2 - 1 : (m + 2) / 3 - 1;
     };
     const int nx = ax_n(p, 0), ny = ax_n(p, 1), n = ax_n(p, 2);
-    // the MHD x pass at nx >= 1024 (2-line tiles, 16-byte rows) measured
-    // faster on unpadded kx planes (41.1 against 42.4 ms at 1024^3)
-    const int bc_pad = (p->solver == PST_MHD && nx >= 1024) ? 0 : BC_PAD;
     P->geo = make_geo(nx, ny, n, cut(nx), cut(ny), cut(n), TWO_PI / ax_len(p, 0), TWO_PI / ax_len(p, 1),
-                      TWO_PI / ax_len(p, 2), gpe ? 1 : 0, bc_pad);
+                      TWO_PI / ax_len(p, 2), gpe ? 1 : 0);
     P->p.n = n;
     const int K = P->geo.K, M = P->geo.M;
     (void)M;
